@@ -1,0 +1,161 @@
+/*
+ * qw.h -- C ABI of the MI355X split-operator propagator for the 2D Dirac
+ * equation (libqw.so, HIP for gfx950).
+ *
+ * What it computes (Ge, Ahrens, Shen, "Two-dimensional simulation of the
+ * spin-flip in the Kapitza-Dirac effect"):
+ *   - the four-component Dirac spinor Psi(x, y) on a periodic nx x ny grid,
+ *     Hamiltonian H = c alpha.(p + A) + beta c^2 in atomic units
+ *     (Sec. II.B, Eq. 5, standard representation, m = hbar = 1);
+ *   - the standing-wave vector potential of two counter-propagating Gaussian
+ *     beams (Sec. II.A, Eq. 1-4) in its paraxial form, evaluated on the GPU;
+ *   - time steps Psi(t + dt) = U(t + dt, t) Psi(t) by the FFT split-operator
+ *     method (Sec. II.D, Eq. 15), in the symmetric order
+ *     V(t_k, dt/2) F^-1 K(dt) F V(t_{k+1}, dt/2) with t_k = t0 + k dt;
+ *   - the Gaussian initial packet (Sec. II.C, Eq. 12-14) and the band and
+ *     spin-resolved probabilities (Sec. III.B, Eq. 18-19).
+ *
+ * Conventions shared by every call:
+ *   - grid points x_i = x_min + i lx / nx (likewise y); momenta
+ *     p = (2 pi / lx) k with k in [-nx/2, nx/2) (the Nyquist column is -nx/2);
+ *   - psi is caller-owned device memory, contiguous [ny][nx][4] complex
+ *     (interleaved re, im), complex128 for QW_F64, complex64 for QW_F32;
+ *   - the workspace is caller-owned device memory of at least
+ *     qw_workspace_bytes() bytes, 256-byte aligned, alive until qw_destroy;
+ *   - the library allocates no device memory; qw_ctx itself is host memory
+ *     owned by the library and released by qw_destroy;
+ *   - every call that takes hip_stream enqueues only on that stream
+ *     (a hipStream_t; NULL is the legacy default stream) and returns without
+ *     waiting, except qw_observables, which waits for its own results;
+ *   - every function returns QW_OK (0) or a negative QW_E_* code, never
+ *     throws and never exits; argument errors are reported before anything
+ *     is enqueued; qw_last_error(ctx) describes the last failure.
+ */
+#ifndef QW_H
+#define QW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QW_OK = 0,
+    QW_E_ARG = -1,       /* null pointer, bad enum, non-finite parameter */
+    QW_E_SIZE = -2,      /* grid size not a power of two in [8, 4096] */
+    QW_E_WORKSPACE = -3, /* workspace too small or misaligned */
+    QW_E_DEVICE = -4,    /* a HIP call failed (sticky device errors included) */
+    QW_E_NUMERIC = -5,   /* a non-finite observable (outputs still written) */
+    QW_E_STATE = -6      /* call out of order (e.g. stepping before qw_set_beam) */
+};
+
+enum { QW_F64 = 0, QW_F32 = 1 };
+
+enum {
+    QW_BEAM_NONE = 0,              /* A = 0: free evolution */
+    QW_BEAM_STANDING_PARAXIAL = 1, /* standing wave, see qw_beam */
+    QW_BEAM_UNIFORM = 2            /* constant A = (ux, uy) */
+};
+
+typedef struct qw_ctx_s *qw_ctx;
+
+/* Grid and arithmetic type.  nx, ny: powers of two, 8 <= n <= 4096.
+ * lx, ly > 0 box lengths; c > 0 the speed of light (137.036 in atomic units).
+ * precision QW_F64: all arithmetic in double.  QW_F32: state, FFT
+ * butterflies and spinor updates in float; the kinetic phase E(p) dt and
+ * the field phase k_L x are formed and reduced modulo 2 pi in double before
+ * the float sin/cos; norms and probabilities are summed in double. */
+typedef struct {
+    int32_t nx, ny;
+    double x_min, y_min, lx, ly;
+    double c;
+    int32_t precision;
+} qw_grid;
+
+/* Vector potential (Sec. II.A, Eq. 1-4, paraxial limit x << x_R, z = 0):
+ *   A_y = a0 exp(-y^2/w0^2) cos(k_L x) cos(w t) f(t)
+ *   A_x = a0 (2 y / (k_L w0^2)) exp(-y^2/w0^2) sin(k_L x) cos(w t) f(t)
+ * with k_L = 2 pi / lambda_l, w = c k_L, and the switch-on
+ * f(t) = sin^2(pi t / (2 T_r)) for t < T_r = ramp_periods * lambda_l / c,
+ * else 1 (ramp_periods = 0: no ramp).  longitudinal = 0 drops A_x.
+ * QW_BEAM_UNIFORM uses the constant (ux, uy) and ignores the rest. */
+typedef struct {
+    int32_t mode;
+    double a0, lambda_l, w0, ramp_periods;
+    int32_t longitudinal;
+    double ux, uy;
+} qw_beam;
+
+/* Initial packet (Sec. II.C, Eq. 12-13):
+ *   phi(p) = exp(-|p - p0|^2 / (4 s_p^2)) u^s(p) exp(-i p.r0),  s_p = 1/(2 sigma_x),
+ * with u^s the unit-normalised positive-energy bispinor of Eq. 9 in the
+ * x-polarised basis chi^+ = (1, 1)/sqrt2 (spin = +1) or chi^- = (1, -1)/sqrt2
+ * (spin = -1); psi = sum_p phi(p) exp(i p.r), normalised to sum |psi|^2 = 1. */
+typedef struct {
+    double p0x, p0y, x0, y0, sigma_x;
+    int32_t spin;
+} qw_packet;
+
+/* Observables (Sec. III.B, Eq. 18-19).  With dk = 2 pi / lx, diffraction
+ * order n collects the momentum columns k (signed index) with
+ * |k - band_ref_idx - 2 n band_half_idx| <= window_idx, i.e. a window about
+ * p_ref + 2 n k_L (p_ref = band_ref_idx dk, k_L = band_half_idx dk).
+ * 0 <= window_idx < band_half_idx, 0 <= n_max <= 16, spin0 = +1 or -1. */
+typedef struct {
+    int32_t band_ref_idx, band_half_idx, window_idx, n_max, spin0;
+} qw_obs_spec;
+
+/* Bytes of workspace a grid needs (twiddle and field tables, reduction
+ * partials and one state-sized plane for qw_observables). */
+int qw_workspace_bytes(const qw_grid *g, size_t *bytes);
+
+/* Validate the grid, bind the workspace and enqueue the twiddle-table
+ * kernel on hip_stream.  On success *out is a new context. */
+int qw_init_grid(qw_ctx *out, const qw_grid *g, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Set the vector potential (host-only; the field tables are rebuilt on the
+ * stream of the next call that needs them). */
+int qw_set_beam(qw_ctx h, const qw_beam *b);
+
+/* Write the normalised initial packet into psi (several kernels). */
+int qw_init_packet(qw_ctx h, void *psi, const qw_packet *e, void *hip_stream);
+
+/* n >= 0 split-operator steps of size dt from t0, in place on psi.
+ * dt may be negative (backward propagation); dt = 0 and n = 0 leave psi as is
+ * (n = 0 enqueues nothing).  2n + 1 kernels: one row pass V(t0, dt/2) F_x,
+ * then n column passes F_y^-1 K(dt) F_y interleaved with n - 1 row passes
+ * F_x V(t_k, dt) F_x^-1, and a last row pass V(t_n, dt/2) F_x^-1. */
+int qw_step_n(qw_ctx h, void *psi, int64_t n, double t0, double dt, void *hip_stream);
+
+/* Observables of psi (not modified) into out_host (host memory), laid out as
+ *   [norm, P_n (B), P_n^+ (B), P_n^- (B), P_flip, P_neg],  B = 2 n_max + 1,
+ * out_len >= 3B + 3.  norm = sum_cells |psi|^2; every P is a ratio to
+ * sum_p |phi(p)|^2: P_n = window sum of |phi|^2, P_n^s = window sum of
+ * |<u^s(p)|phi(p)>|^2, P_flip = sum over all p of |<u^{-spin0}|phi>|^2,
+ * P_neg = 1 - sum_p (|c^+|^2 + |c^-|^2) (the negative-energy share).
+ * Waits for hip_stream.  Returns QW_E_NUMERIC if any output is not finite. */
+int qw_observables(qw_ctx h, const void *psi, const qw_obs_spec *o, double *out_host, int32_t out_len,
+                   void *hip_stream);
+
+/* Per-kernel timing for profiling: with enable = 1, every later launch of a
+ * row or column pass by qw_step_n is bracketed by HIP events on its stream.
+ * qw_kernel_times waits for the stream and writes
+ *   out[0] = row-pass launches, out[1] = their total ms,
+ *   out[2] = column-pass launches, out[3] = their total ms  (out_len >= 4),
+ * then clears the counters.  Enabling adds event records between launches. */
+int qw_kernel_timing(qw_ctx h, int enable);
+int qw_kernel_times(qw_ctx h, double *out, int32_t out_len, void *hip_stream);
+
+/* Message of the last failure on h (or of the last failed qw_init_grid when
+ * h is NULL).  Valid until the next call on h. */
+const char *qw_last_error(qw_ctx h);
+
+/* Release the context (not the caller's psi or workspace).  NULL is a no-op. */
+void qw_destroy(qw_ctx h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QW_H */

@@ -1,0 +1,471 @@
+// qw_api.cpp -- host engine behind the C ABI of include/qw.h: argument
+// validation, workspace carving, table set-up and the launch sequence of the
+// split-operator step.  No device memory is allocated here; every launch goes
+// to the caller's stream.
+#include "../../include/qw.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qw_launch.hpp"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kMaxNmax = 16;
+constexpr int kPartialStride = 3 * (2 * kMaxNmax + 1) + 3;  // doubles per column-pass workgroup
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool is_pow2_in_range(int n) { return n >= 8 && n <= 4096 && (n & (n - 1)) == 0; }
+
+// workspace layout (byte offsets from the start, each 256-aligned)
+struct Layout {
+    size_t scalars;   // 256 doubles: [0] packet norm, [8..) observables results
+    size_t twx, twy;  // twiddle tables
+    size_t bx, by;    // field tables
+    size_t rownorm;   // ny doubles
+    size_t partial;   // column-pass workgroups x kPartialStride doubles
+    size_t plane;     // one state-sized array
+    size_t total;
+};
+
+Layout make_layout(const qw_grid& g)
+{
+    const size_t cs = g.precision == QW_F32 ? 8 : 16;  // bytes per complex
+    const int nblk_max = g.nx;                         // column workgroups never exceed nx
+    Layout L;
+    size_t o = 0;
+    L.scalars = o;
+    o = align_up(o + 256 * sizeof(double));
+    L.twx = o;
+    o = align_up(o + (size_t)g.nx * cs);
+    L.twy = o;
+    o = align_up(o + (size_t)g.ny * cs);
+    L.bx = o;
+    o = align_up(o + (size_t)g.nx * cs);
+    L.by = o;
+    o = align_up(o + (size_t)g.ny * cs);
+    L.rownorm = o;
+    o = align_up(o + (size_t)g.ny * sizeof(double));
+    L.partial = o;
+    o = align_up(o + (size_t)nblk_max * kPartialStride * sizeof(double));
+    L.plane = o;
+    o = align_up(o + (size_t)g.nx * g.ny * 4 * cs);
+    L.total = o;
+    return L;
+}
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kind;  // 0 row, 1 column
+};
+
+}  // namespace
+
+struct qw_ctx_s {
+    qw_grid g{};
+    qw_beam b{};
+    bool beam_set = false;
+    bool tables_dirty = true;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay{};
+    int device = 0;
+    std::string err;
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(qw_ctx h, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_init_error = buf;
+    return code;
+}
+
+int hip_fail(qw_ctx h, hipError_t e, const char* what)
+{
+    return fail(h, QW_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_all(std::initializer_list<double> v)
+{
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+int check_grid(const qw_grid* g)
+{
+    if (!g) return fail(nullptr, QW_E_ARG, "grid is NULL");
+    if (!is_pow2_in_range(g->nx) || !is_pow2_in_range(g->ny))
+        return fail(nullptr, QW_E_SIZE, "nx=%d ny=%d: each must be a power of two in [8, 4096]", g->nx, g->ny);
+    if (g->precision != QW_F32 && g->precision != QW_F64)
+        return fail(nullptr, QW_E_ARG, "precision %d is neither QW_F64 nor QW_F32", g->precision);
+    if (!finite_all({g->x_min, g->y_min, g->lx, g->ly, g->c}) || !(g->lx > 0) || !(g->ly > 0) || !(g->c > 0))
+        return fail(nullptr, QW_E_ARG, "box and c must be finite with lx, ly, c > 0");
+    return QW_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool f32(const qw_ctx h) { return h->g.precision == QW_F32; }
+
+hipError_t launch_row(qw_ctx h, int mode, const qw::RowArgs& a, hipStream_t s)
+{
+    return f32(h) ? qw::launch_row_f32(mode, h->g.nx, a, s) : qw::launch_row_f64(mode, h->g.nx, a, s);
+}
+
+hipError_t launch_col(qw_ctx h, int mode, const qw::ColArgs& a, hipStream_t s)
+{
+    return f32(h) ? qw::launch_col_f32(mode, h->g.ny, a, s) : qw::launch_col_f64(mode, h->g.ny, a, s);
+}
+
+int col_blocks(qw_ctx h) { return f32(h) ? qw::col_blocks_f32(h->g.nx, h->g.ny) : qw::col_blocks_f64(h->g.nx, h->g.ny); }
+
+hipEvent_t pooled_event(qw_ctx h)
+{
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// bracket a launch with events when timing is on
+template <typename F>
+hipError_t timed(qw_ctx h, int kind, hipStream_t s, F&& launch)
+{
+    if (!h->timing) return launch();
+    TimedLaunch t{pooled_event(h), pooled_event(h), kind};
+    if (!t.a || !t.b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(t.a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(t.b, s);
+    h->timed.push_back(t);
+    return e;
+}
+
+int ensure_tables(qw_ctx h, hipStream_t s)
+{
+    if (!h->tables_dirty) return QW_OK;
+    const qw_beam& b = h->b;
+    qw::BeamArgs a{};
+    a.mode = b.mode;
+    a.longitudinal = b.longitudinal;
+    a.nx = h->g.nx;
+    a.ny = h->g.ny;
+    a.x_min = h->g.x_min;
+    a.y_min = h->g.y_min;
+    a.lx = h->g.lx;
+    a.ly = h->g.ly;
+    a.a0 = b.a0;
+    a.kl = b.mode == QW_BEAM_STANDING_PARAXIAL ? 2.0 * kPi / b.lambda_l : 0.0;
+    a.w0 = b.w0;
+    a.ux = b.ux;
+    a.uy = b.uy;
+    void* bx = h->ws + h->lay.bx;
+    void* by = h->ws + h->lay.by;
+    hipError_t e = f32(h) ? qw::launch_beam_tables_f32(bx, by, a, s) : qw::launch_beam_tables_f64(bx, by, a, s);
+    if (e != hipSuccess) return hip_fail(h, e, "field table kernel");
+    h->tables_dirty = false;
+    return QW_OK;
+}
+
+qw::RowArgs row_args(qw_ctx h, const void* src, void* dst)
+{
+    qw::RowArgs a{};
+    a.src = src;
+    a.dst = dst;
+    a.twx = h->ws + h->lay.twx;
+    a.beam_x = h->ws + h->lay.bx;
+    a.beam_y = h->ws + h->lay.by;
+    a.rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
+    a.scale_src = reinterpret_cast<const double*>(h->ws + h->lay.scalars);
+    const qw_beam& b = h->b;
+    a.beam_mode = h->beam_set ? b.mode : QW_BEAM_NONE;
+    if (b.mode == QW_BEAM_STANDING_PARAXIAL) {
+        a.omega = h->g.c * 2.0 * kPi / b.lambda_l;
+        a.t_ramp = b.ramp_periods * b.lambda_l / h->g.c;
+        a.ramp_k = a.t_ramp > 0 ? kPi / (2.0 * a.t_ramp) : 0.0;
+    }
+    a.c = h->g.c;
+    a.ny = h->g.ny;
+    return a;
+}
+
+qw::ColArgs col_args(qw_ctx h, void* psi)
+{
+    qw::ColArgs a{};
+    a.psi = psi;
+    a.twy = h->ws + h->lay.twy;
+    a.nx = h->g.nx;
+    a.dkx = 2.0 * kPi / h->g.lx;
+    a.dky = 2.0 * kPi / h->g.ly;
+    a.c = h->g.c;
+    a.inv_cells = 1.0 / ((double)h->g.nx * (double)h->g.ny);
+    a.partial = reinterpret_cast<double*>(h->ws + h->lay.partial);
+    a.partial_stride = kPartialStride;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qw_workspace_bytes(const qw_grid* g, size_t* bytes)
+{
+    int rc = check_grid(g);
+    if (rc != QW_OK) return rc;
+    if (!bytes) return fail(nullptr, QW_E_ARG, "bytes is NULL");
+    *bytes = make_layout(*g).total;
+    return QW_OK;
+}
+
+int qw_init_grid(qw_ctx* out, const qw_grid* g, void* workspace, size_t ws_bytes, void* hip_stream)
+{
+    if (!out) return fail(nullptr, QW_E_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_grid(g);
+    if (rc != QW_OK) return rc;
+    Layout lay = make_layout(*g);
+    if (!workspace) return fail(nullptr, QW_E_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(nullptr, QW_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < lay.total)
+        return fail(nullptr, QW_E_WORKSPACE, "workspace has %zu bytes, the grid needs %zu", ws_bytes, lay.total);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(nullptr, QW_E_ARG, "workspace is not device memory");
+    }
+    qw_ctx h = new (std::nothrow) qw_ctx_s;
+    if (!h) return fail(nullptr, QW_E_DEVICE, "out of host memory");
+    h->g = *g;
+    h->ws = static_cast<char*>(workspace);
+    h->ws_bytes = ws_bytes;
+    h->lay = lay;
+    h->device = attr.device;
+    hipStream_t s = as_stream(hip_stream);
+    hipError_t e = f32(h) ? qw::launch_twiddles_f32(h->ws + lay.twx, g->nx, s)
+                          : qw::launch_twiddles_f64(h->ws + lay.twx, g->nx, s);
+    if (e == hipSuccess)
+        e = f32(h) ? qw::launch_twiddles_f32(h->ws + lay.twy, g->ny, s)
+                   : qw::launch_twiddles_f64(h->ws + lay.twy, g->ny, s);
+    if (e != hipSuccess) {
+        fail(nullptr, QW_E_DEVICE, "twiddle kernel: %s", hipGetErrorString(e));
+        delete h;
+        return QW_E_DEVICE;
+    }
+    // field tables start as A = 0 until qw_set_beam
+    h->b.mode = QW_BEAM_NONE;
+    rc = ensure_tables(h, s);
+    if (rc != QW_OK) {
+        g_init_error = h->err;
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return QW_OK;
+}
+
+int qw_set_beam(qw_ctx h, const qw_beam* b)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!b) return fail(h, QW_E_ARG, "beam is NULL");
+    if (b->mode != QW_BEAM_NONE && b->mode != QW_BEAM_STANDING_PARAXIAL && b->mode != QW_BEAM_UNIFORM)
+        return fail(h, QW_E_ARG, "unknown beam mode %d", b->mode);
+    if (b->mode == QW_BEAM_STANDING_PARAXIAL) {
+        if (!finite_all({b->a0, b->lambda_l, b->w0, b->ramp_periods}) || !(b->lambda_l > 0) || !(b->w0 > 0) ||
+            b->ramp_periods < 0)
+            return fail(h, QW_E_ARG, "standing wave needs finite a0, lambda_l > 0, w0 > 0, ramp_periods >= 0");
+    }
+    if (b->mode == QW_BEAM_UNIFORM && !finite_all({b->ux, b->uy}))
+        return fail(h, QW_E_ARG, "uniform field must be finite");
+    h->b = *b;
+    h->beam_set = true;
+    h->tables_dirty = true;
+    return QW_OK;
+}
+
+int qw_init_packet(qw_ctx h, void* psi, const qw_packet* e, void* hip_stream)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!psi || !e) return fail(h, QW_E_ARG, "psi or packet is NULL");
+    if (!finite_all({e->p0x, e->p0y, e->x0, e->y0, e->sigma_x}) || !(e->sigma_x > 0) ||
+        (e->spin != 1 && e->spin != -1))
+        return fail(h, QW_E_ARG, "packet needs finite values, sigma_x > 0 and spin = +1 or -1");
+    hipStream_t s = as_stream(hip_stream);
+    qw::PacketArgs p{};
+    p.nx = h->g.nx;
+    p.ny = h->g.ny;
+    p.spin = e->spin;
+    p.dkx = 2.0 * kPi / h->g.lx;
+    p.dky = 2.0 * kPi / h->g.ly;
+    p.c = h->g.c;
+    p.p0x = e->p0x;
+    p.p0y = e->p0y;
+    p.x0 = e->x0;
+    p.y0 = e->y0;
+    p.sigma_x = e->sigma_x;
+    p.x_min = h->g.x_min;
+    p.y_min = h->g.y_min;
+    double* rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
+    double* total = reinterpret_cast<double*>(h->ws + h->lay.scalars);
+    hipError_t err = f32(h) ? qw::launch_packet_f32(psi, rownorm, p, s) : qw::launch_packet_f64(psi, rownorm, p, s);
+    if (err == hipSuccess) err = qw::launch_sum_rows(rownorm, h->g.ny, total, s);
+    if (err == hipSuccess) err = launch_col(h, qw::COL_INV, col_args(h, psi), s);
+    if (err == hipSuccess) err = launch_row(h, qw::ROW_INV_SCALE, row_args(h, psi, psi), s);
+    if (err != hipSuccess) return hip_fail(h, err, "packet kernels");
+    return QW_OK;
+}
+
+int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_stream)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!psi) return fail(h, QW_E_ARG, "psi is NULL");
+    if (n < 0) return fail(h, QW_E_ARG, "n = %lld is negative", (long long)n);
+    if (!finite_all({t0, dt})) return fail(h, QW_E_ARG, "t0 and dt must be finite");
+    if (!h->beam_set) return fail(h, QW_E_STATE, "qw_set_beam has not been called");
+    if (n == 0) return QW_OK;
+    if (h->b.mode == QW_BEAM_STANDING_PARAXIAL) {
+        // the in-kernel phase reduction is exact for |w t| < 2^20 pi/2
+        const double om = h->g.c * 2.0 * kPi / h->b.lambda_l;
+        const double tmax = std::fmax(std::fabs(t0), std::fabs(t0 + (double)n * dt));
+        if (om * tmax > 1.6e6) return fail(h, QW_E_ARG, "|omega t| = %g exceeds 1.6e6", om * tmax);
+    }
+    hipStream_t s = as_stream(hip_stream);
+    int rc = ensure_tables(h, s);
+    if (rc != QW_OK) return rc;
+    qw::RowArgs r = row_args(h, psi, psi);
+    r.t0 = t0;
+    r.dt = dt;
+    qw::ColArgs c = col_args(h, psi);
+    c.dt = dt;
+    hipError_t e;
+    // V(t0, dt/2) then F_x
+    r.k = 0;
+    r.tau_frac = 0.5;
+    e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_FIRST, r, s); });
+    for (int64_t k = 1; k <= n && e == hipSuccess; ++k) {
+        e = timed(h, 1, s, [&] { return launch_col(h, qw::COL_PROP, c, s); });
+        if (e != hipSuccess) break;
+        r.k = k;
+        if (k < n) {
+            r.tau_frac = 1.0;  // V(t_k, dt/2) V(t_k, dt/2) = V(t_k, dt)
+            e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_MID, r, s); });
+        } else {
+            r.tau_frac = 0.5;
+            e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_LAST, r, s); });
+        }
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "step kernels");
+    return QW_OK;
+}
+
+int qw_observables(qw_ctx h, const void* psi, const qw_obs_spec* o, double* out_host, int32_t out_len,
+                   void* hip_stream)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!psi || !o || !out_host) return fail(h, QW_E_ARG, "psi, spec or out is NULL");
+    if (o->n_max < 0 || o->n_max > kMaxNmax) return fail(h, QW_E_ARG, "n_max must be in [0, %d]", kMaxNmax);
+    if (o->band_half_idx <= 0 || o->window_idx < 0 || o->window_idx >= o->band_half_idx)
+        return fail(h, QW_E_ARG, "need band_half_idx > 0 and 0 <= window_idx < band_half_idx");
+    if (o->spin0 != 1 && o->spin0 != -1) return fail(h, QW_E_ARG, "spin0 must be +1 or -1");
+    const int nb = 2 * o->n_max + 1;
+    if (out_len < 3 * nb + 3) return fail(h, QW_E_ARG, "out_len %d < %d", out_len, 3 * nb + 3);
+    hipStream_t s = as_stream(hip_stream);
+    void* plane = h->ws + h->lay.plane;
+    double* rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
+    double* results = reinterpret_cast<double*>(h->ws + h->lay.scalars) + 8;
+    qw::ColArgs c = col_args(h, plane);
+    c.band_ref = o->band_ref_idx;
+    c.band_half = o->band_half_idx;
+    c.window = o->window_idx;
+    c.n_max = o->n_max;
+    c.spin0 = o->spin0;
+    hipError_t e = launch_row(h, qw::ROW_FWD_NORM, row_args(h, psi, plane), s);
+    if (e == hipSuccess) e = launch_col(h, qw::COL_OBS, c, s);
+    if (e == hipSuccess)
+        e = qw::launch_obs_finish(rownorm, h->g.ny, c.partial, col_blocks(h), kPartialStride, o->n_max, results, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, results, sizeof(double) * (3 * nb + 3), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "observables");
+    for (int i = 0; i < 3 * nb + 3; ++i)
+        if (!std::isfinite(out_host[i])) return fail(h, QW_E_NUMERIC, "observable %d is not finite", i);
+    return QW_OK;
+}
+
+int qw_kernel_timing(qw_ctx h, int enable)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    h->timing = enable != 0;
+    return QW_OK;
+}
+
+int qw_kernel_times(qw_ctx h, double* out, int32_t out_len, void* hip_stream)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!out || out_len < 4) return fail(h, QW_E_ARG, "out needs 4 doubles");
+    hipError_t e = hipStreamSynchronize(as_stream(hip_stream));
+    if (e != hipSuccess) return hip_fail(h, e, "stream synchronize");
+    double cnt[2] = {0, 0}, ms[2] = {0, 0};
+    for (auto& t : h->timed) {
+        float v = 0.f;
+        if (hipEventElapsedTime(&v, t.a, t.b) == hipSuccess) {
+            cnt[t.kind] += 1;
+            ms[t.kind] += v;
+        }
+        h->event_pool.push_back(t.a);
+        h->event_pool.push_back(t.b);
+    }
+    h->timed.clear();
+    out[0] = cnt[0];
+    out[1] = ms[0];
+    out[2] = cnt[1];
+    out[3] = ms[1];
+    return QW_OK;
+}
+
+const char* qw_last_error(qw_ctx h)
+{
+    if (!h) return g_init_error.c_str();
+    return h->err.c_str();
+}
+
+void qw_destroy(qw_ctx h)
+{
+    if (!h) return;
+    for (auto& t : h->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : h->event_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+}  // extern "C"

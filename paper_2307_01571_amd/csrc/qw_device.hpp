@@ -1,0 +1,408 @@
+// qw_device.hpp -- device building blocks for the split-operator passes on gfx950:
+// complex arithmetic, radix-2/4/8/16 register butterflies, the Stockham
+// transform staged through LDS, and the closed-form 2x2 block propagators.
+//
+// Block structure (Sec. II.B, Eq. 5 with p_z = A_z = 0, standard
+// representation): H = c alpha.(p + A) + beta c^2 never couples (psi1, psi4)
+// with (psi2, psi3).  Both the kinetic propagator exp(-i H0 dt) and the
+// interaction propagator exp(-i c alpha.A dt) therefore act as two 2x2
+// blocks, and each is cos(phase) I - i sin(phase) M/|M| because
+// H0^2 = E^2 I and (alpha.A)^2 = |A|^2 I.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qw {
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a)
+{
+    return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// ---------------------------------------------------------------------------
+// Buffer addressing (gfx9 raw buffers): one 128-bit resource in SGPRs, a
+// 32-bit per-lane byte offset and a wave-uniform scalar offset.  The state
+// arrays are at most 1 GiB, so 32-bit offsets cover them; accesses past
+// num_records read zero and drop writes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ cx<float> bload(cx<float>*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ cx<double> bload(cx<double>*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+typedef int qw_v2i __attribute__((ext_vector_type(2)));
+typedef int qw_v4i __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void bstore(cx<float> v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qw_v2i, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(cx<double> v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qw_v4i, v), r, voff, soff, 0);
+}
+
+// ---------------------------------------------------------------------------
+// sin and cos of a phase given in double.  x = k pi/2 + r with pi/2 split in
+// three parts of which the first two have 33-bit mantissas (so k P1 and k P2
+// are exact for |k| < 2^20), |r| <= pi/4, then the Taylor series of sin and
+// cos about 0: to r^17 / r^18 in double (truncation < 1e-17), to r^11 / r^12
+// in float (truncation < 1e-9).  Quadrant k mod 4 selects and signs.
+// ---------------------------------------------------------------------------
+constexpr double kPio2a = 1.5707963267341256;      // 0x1.921fb544p+0
+constexpr double kPio2b = 6.077100506303966e-11;   // 0x1.0b4611a6p-34
+constexpr double kPio2c = 2.0222662487959506e-21;
+constexpr double kTwoOverPi = 0.6366197723675814;
+
+__device__ __forceinline__ double reduce_quadrant(double x, int& q)
+{
+    const double k = rint(x * kTwoOverPi);
+    double r = fma(-k, kPio2a, x);
+    r = fma(-k, kPio2b, r);
+    r = fma(-k, kPio2c, r);
+    q = (int)(long long)k & 3;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void quadrant(int q, T sr, T cr, T& s, T& c)
+{
+    const bool swap = q & 1;
+    const T a = swap ? cr : sr, b = swap ? sr : cr;
+    s = (q == 1 || q == 0) ? a : -a;
+    c = (q == 0 || q == 3) ? b : -b;
+}
+
+__device__ __forceinline__ void sincos_phase(double x, double& s, double& c)
+{
+    int q;
+    const double r = reduce_quadrant(x, q);
+    const double r2 = r * r;
+    double ps = 2.8114572543455206e-15;  // 1/17!
+    ps = fma(ps, r2, -7.647163731819816e-13);
+    ps = fma(ps, r2, 1.6059043836821613e-10);
+    ps = fma(ps, r2, -2.505210838544172e-08);
+    ps = fma(ps, r2, 2.7557319223985893e-06);
+    ps = fma(ps, r2, -0.0001984126984126984);
+    ps = fma(ps, r2, 0.008333333333333333);
+    ps = fma(ps, r2, -0.16666666666666666);
+    const double sr = fma(ps * r2, r, r);
+    double pc = 1.5619206968586225e-16;  // 1/18!
+    pc = fma(pc, r2, -4.779477332387385e-14);
+    pc = fma(pc, r2, 1.1470745597729725e-11);
+    pc = fma(pc, r2, -2.08767569878681e-09);
+    pc = fma(pc, r2, 2.755731922398589e-07);
+    pc = fma(pc, r2, -2.48015873015873e-05);
+    pc = fma(pc, r2, 0.001388888888888889);
+    pc = fma(pc, r2, -0.041666666666666664);
+    pc = fma(pc, r2, 0.5);
+    const double cr = fma(-pc, r2, 1.0);
+    quadrant(q, sr, cr, s, c);
+}
+
+__device__ __forceinline__ void sincos_phase(double x, float& s, float& c)
+{
+    int q;
+    const float r = (float)reduce_quadrant(x, q);
+    const float r2 = r * r;
+    float ps = -2.505210838544172e-08f;  // -1/11!
+    ps = fmaf(ps, r2, 2.7557319223985893e-06f);
+    ps = fmaf(ps, r2, -0.0001984126984126984f);
+    ps = fmaf(ps, r2, 0.008333333333333333f);
+    ps = fmaf(ps, r2, -0.16666666666666666f);
+    const float sr = fmaf(ps * r2, r, r);
+    float pc = 2.08767569878681e-09f;  // 1/12!
+    pc = fmaf(pc, r2, -2.755731922398589e-07f);
+    pc = fmaf(pc, r2, 2.48015873015873e-05f);
+    pc = fmaf(pc, r2, -0.001388888888888889f);
+    pc = fmaf(pc, r2, 0.041666666666666664f);
+    pc = fmaf(pc, r2, -0.5f);
+    const float cr = fmaf(pc, r2, 1.0f);
+    quadrant(q, sr, cr, s, c);
+}
+
+// ---------------------------------------------------------------------------
+// Register DFTs.  Forward: X[k] = sum_n x[n] exp(-2 pi i n k / R); inverse
+// uses exp(+...), unnormalised.  Radix 8 and 16 split as Q x 4 with the
+// inner twiddles exp(-+2 pi i q s / R) as literal constants.
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b)
+{
+    cx<T> s = add(a, b), d = sub(a, b);
+    a = s;
+    b = d;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>& x0, cx<T>& x1, cx<T>& x2, cx<T>& x3)
+{
+    cx<T> s02 = add(x0, x2), d02 = sub(x0, x2);
+    cx<T> s13 = add(x1, x3), d13 = rot90<T, INV>(sub(x1, x3));
+    x0 = add(s02, s13);
+    x2 = sub(s02, s13);
+    x1 = add(d02, d13);
+    x3 = sub(d02, d13);
+}
+
+// cos/sin(2 pi j / 16), j = 0..15 (literal constants)
+struct tw16 {
+    static constexpr double c[16] = {1.0,
+                                     0.92387953251128675613,
+                                     0.70710678118654752440,
+                                     0.38268343236508977173,
+                                     0.0,
+                                     -0.38268343236508977173,
+                                     -0.70710678118654752440,
+                                     -0.92387953251128675613,
+                                     -1.0,
+                                     -0.92387953251128675613,
+                                     -0.70710678118654752440,
+                                     -0.38268343236508977173,
+                                     0.0,
+                                     0.38268343236508977173,
+                                     0.70710678118654752440,
+                                     0.92387953251128675613};
+    static constexpr double s[16] = {0.0,
+                                     0.38268343236508977173,
+                                     0.70710678118654752440,
+                                     0.92387953251128675613,
+                                     1.0,
+                                     0.92387953251128675613,
+                                     0.70710678118654752440,
+                                     0.38268343236508977173,
+                                     0.0,
+                                     -0.38268343236508977173,
+                                     -0.70710678118654752440,
+                                     -0.92387953251128675613,
+                                     -1.0,
+                                     -0.92387953251128675613,
+                                     -0.70710678118654752440,
+                                     -0.38268343236508977173};
+};
+
+// multiply by exp(-+2 pi i j / 16) with j a compile-time constant
+template <typename T, bool INV, int J>
+__device__ __forceinline__ cx<T> tw16mul(cx<T> a)
+{
+    constexpr int j = J & 15;
+    if constexpr (j == 0) return a;
+    else if constexpr (j == 4) return rot90<T, INV>(a);
+    else if constexpr (j == 8) return cx<T>{-a.re, -a.im};
+    else if constexpr (j == 12) return rot90<T, !INV>(a);
+    else {
+        const T c = (T)tw16::c[j];
+        const T s = INV ? (T)tw16::s[j] : (T)-tw16::s[j];
+        return cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+    }
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cx<T>* x)
+{
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) {
+        dft2<T, INV>(x[0], x[1]);
+    } else if constexpr (R == 4) {
+        dft4<T, INV>(x[0], x[1], x[2], x[3]);
+    } else if constexpr (R == 8) {
+        // n = q + 2 l (q < 2, l < 4), k = s + 4 u (s < 4, u < 2)
+        dft4<T, INV>(x[0], x[2], x[4], x[6]);
+        dft4<T, INV>(x[1], x[3], x[5], x[7]);
+        // twiddle exp(-+2 pi i q s / 8) = w16^(2 q s) on the q = 1 row
+        x[3] = tw16mul<T, INV, 2>(x[3]);
+        x[5] = tw16mul<T, INV, 4>(x[5]);
+        x[7] = tw16mul<T, INV, 6>(x[7]);
+        cx<T> y[8];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            cx<T> a = x[2 * s], b = x[2 * s + 1];
+            y[s] = add(a, b);
+            y[s + 4] = sub(a, b);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = y[k];
+    } else if constexpr (R == 16) {
+        // n = q + 4 l (q, l < 4), k = s + 4 u (s, u < 4)
+        cx<T> y[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cx<T> a = x[q], b = x[q + 4], c = x[q + 8], d = x[q + 12];
+            dft4<T, INV>(a, b, c, d);  // index s = 0..3
+            y[4 * q + 0] = a;
+            y[4 * q + 1] = b;
+            y[4 * q + 2] = c;
+            y[4 * q + 3] = d;
+        }
+        // twiddles w16^(q s)
+        y[4 * 1 + 1] = tw16mul<T, INV, 1>(y[5]);
+        y[4 * 1 + 2] = tw16mul<T, INV, 2>(y[6]);
+        y[4 * 1 + 3] = tw16mul<T, INV, 3>(y[7]);
+        y[4 * 2 + 1] = tw16mul<T, INV, 2>(y[9]);
+        y[4 * 2 + 2] = tw16mul<T, INV, 4>(y[10]);
+        y[4 * 2 + 3] = tw16mul<T, INV, 6>(y[11]);
+        y[4 * 3 + 1] = tw16mul<T, INV, 3>(y[13]);
+        y[4 * 3 + 2] = tw16mul<T, INV, 6>(y[14]);
+        y[4 * 3 + 3] = tw16mul<T, INV, 9>(y[15]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            cx<T> a = y[s], b = y[4 + s], c = y[8 + s], d = y[12 + s];
+            dft4<T, INV>(a, b, c, d);  // index u = 0..3
+            x[s] = a;
+            x[s + 4] = b;
+            x[s + 8] = c;
+            x[s + 12] = d;
+        }
+    } else {
+        static_assert(R == 16, "radix must be 1, 2, 4, 8 or 16");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stockham transform of length N over a group of NT = N/E threads.
+//
+// Ownership: before and after every pass, thread t of a sequence holds the
+// elements at positions t + NT m, m = 0..E-1.  A pass of radix R with
+// stride NS takes the butterflies j = t + NT b (b < E/R), whose inputs
+// j + r N/R are exactly the thread's slots b + r E/R, applies the twiddles
+// w^(r (j mod NS)) with w = exp(-+2 pi i / (NS R)), does the radix-R DFT and
+// writes output r to position (j / NS) NS R + (j mod NS) + r NS.  Between
+// passes the outputs go through LDS; after the last pass (NS R = N) every
+// output position equals an input position of the same thread, so the
+// result is already in natural order in the same slots.
+// ---------------------------------------------------------------------------
+template <int... R>
+struct sched {};
+
+// LDS padding: one extra element every 32 breaks the power-of-two strides
+__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> 5); }
+template <int N>
+struct lds_len {
+    static constexpr int value = N + N / 32;
+};
+
+template <typename T, int N, int E, int NC, bool INV, int NS, int R>
+__device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw)
+{
+    constexpr int NT = N / E;
+    constexpr int B = E / R;
+    static_assert(E % R == 0, "radix must divide the per-thread element count");
+    // keep this pass's twiddle loads and their offsets inside the pass:
+    // hoisting or sharing them across passes would hold them all in registers
+    asm volatile("" ::: "memory");
+    int tt = t;
+    asm volatile("" : "+v"(tt));
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = tt + NT * b;
+        cx<T> w[R];
+        if constexpr (NS > 1) {
+            const int jm = j & (NS - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> tv = tw[(jm * r) * (N / (NS * R))];
+                w[r] = INV ? conj(tv) : tv;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            cx<T> x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = v[c][b + r * B];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) x[r] = mul(x[r], w[r]);
+            }
+            dft<T, R, INV>(x);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c][b + r * B] = x[r];
+        }
+    }
+}
+
+// Move one component from pass-output order to the next pass's slots via LDS.
+template <typename T, int N, int E, int NS, int R>
+__device__ __forceinline__ void fft_exchange(cx<T> (&vc)[E], int t, cx<T>* lds)
+{
+    constexpr int NT = N / E;
+    constexpr int B = E / R;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + NT * b;
+        const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lpad(base + r * NS)] = vc[b + r * B];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) vc[m] = lds[lpad(t + NT * m)];
+    __syncthreads();
+}
+
+template <typename T, int N, int E, int NC, bool INV, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_run(cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw, cx<T>* lds)
+{
+    fft_pass<T, N, E, NC, INV, NS, R>(v, t, tw);
+    if constexpr (sizeof...(Rest) > 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fft_exchange<T, N, E, NS, R>(v[c], t, lds);
+        fft_run<T, N, E, NC, INV, NS * R, Rest...>(v, t, tw, lds);
+    }
+}
+
+template <typename T, int N, int E, int NC, bool INV, int... R>
+__device__ __forceinline__ void fft(sched<R...>, cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw, cx<T>* lds)
+{
+    fft_run<T, N, E, NC, INV, 1, R...>(v, t, tw, lds);
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 block propagator  P = C I - i (a sigma_z + bx sigma_x + by sigma_y)
+// acting on (top, bot).  Block A = (psi1, psi4) takes by as given, block
+// B = (psi2, psi3) takes -by:
+//   top' = (C - i a) top + (-by - i bx) bot
+//   bot' = ( by - i bx) top + (C + i a) bot
+// Kinetic: C = cos(E dt), (a, bx, by) = sin(E dt)/E (c^2, c px, c py).
+// Interaction: C = cos(c|A| dt), a = 0, (bx, by) = sin(c|A| dt)/|A| (Ax, Ay).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void block_prop(cx<T>& top, cx<T>& bot, T C, T a, T bx, T by)
+{
+    const cx<T> t = {C * top.re + a * top.im - by * bot.re + bx * bot.im,
+                     C * top.im - a * top.re - by * bot.im - bx * bot.re};
+    const cx<T> b = {by * top.re + bx * top.im + C * bot.re - a * bot.im,
+                     by * top.im - bx * top.re + C * bot.im + a * bot.re};
+    top = t;
+    bot = b;
+}
+
+}  // namespace qw

@@ -1,0 +1,582 @@
+// qw_kernels.inl -- the HIP kernels of the split-operator step, templated on the
+// arithmetic type T (float or double) and the transform lengths.  Included by
+// qw_kernels_f32.hip and qw_kernels_f64.hip, which instantiate one precision
+// each.
+//
+// Data layout in HBM: psi[ny][nx][4] complex T, x fastest.  Between the
+// kernels of one qw_step_n call the array holds the mixed representation
+// (kx, y): row passes transform along x, column passes along y.
+//
+//   row pass    (one workgroup = RPW whole rows):
+//       load row -> [F_x^-1] -> V(t, tau) -> [F_x] -> store
+//   column pass (one workgroup = TX whole columns):
+//       load columns -> F_y -> K(dt)/(nx ny) -> F_y^-1 -> store
+//
+// Each pass reads and writes the state once: 64 B per cell per pass in FP32,
+// 128 B in FP64.
+#pragma once
+#include "qw_device.hpp"
+#include "qw_launch.hpp"
+
+#ifndef QW_WPE
+#define QW_WPE 2  // minimum waves per SIMD the register allocation must allow
+#endif
+
+namespace qw {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+
+// ---------------------------------------------------------------------------
+// transform plans: elements per thread E and the radix schedule per length
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+struct plan;
+
+#define QW_PLAN(TYPE, NN, EE, ...)                 \
+    template <>                                     \
+    struct plan<TYPE, NN> {                         \
+        static constexpr int E = EE;                \
+        using S = sched<__VA_ARGS__>;               \
+    };
+
+QW_PLAN(float, 8, 8, 8)
+QW_PLAN(float, 16, 16, 16)
+QW_PLAN(float, 32, 16, 8, 4)
+QW_PLAN(float, 64, 16, 16, 4)
+QW_PLAN(float, 128, 16, 16, 8)
+QW_PLAN(float, 256, 16, 16, 16)
+QW_PLAN(float, 512, 16, 16, 8, 4)
+QW_PLAN(float, 1024, 16, 16, 16, 4)
+QW_PLAN(float, 2048, 16, 16, 16, 8)
+QW_PLAN(float, 4096, 16, 16, 16, 16)
+QW_PLAN(double, 8, 8, 8)
+QW_PLAN(double, 16, 8, 4, 4)
+QW_PLAN(double, 32, 8, 8, 4)
+QW_PLAN(double, 64, 8, 8, 8)
+QW_PLAN(double, 128, 8, 8, 4, 4)
+QW_PLAN(double, 256, 8, 8, 8, 4)
+QW_PLAN(double, 512, 8, 8, 8, 8)
+QW_PLAN(double, 1024, 8, 8, 8, 4, 4)
+QW_PLAN(double, 2048, 8, 8, 8, 8, 4)
+QW_PLAN(double, 4096, 8, 8, 8, 8, 8)
+#undef QW_PLAN
+
+// Lanes come in pairs: lane 2q + 0 holds spin block A = (psi1, psi4) and
+// lane 2q + 1 block B = (psi2, psi3) of the same cells, so a line of length N
+// takes L = 2 N/E lanes and each lane keeps 2 E complex values in registers.
+template <typename T, int N>
+struct shape {
+    static constexpr int E = plan<T, N>::E;
+    static constexpr int NT = N / E;                                  // lanes per line and block
+    static constexpr int L = 2 * NT;                                  // lanes per line
+    static constexpr int RPW = L >= 256 ? 1 : 256 / L;                // rows per workgroup
+    static constexpr int TX = L >= 512 ? 1 : (L >= 128 ? 2 : 256 / L);  // columns per workgroup
+    static constexpr int LL = lds_len<N>::value;
+};
+
+// ---------------------------------------------------------------------------
+// scalar helpers
+// ---------------------------------------------------------------------------
+// time factor of the standing wave: f(t) cos(w t), f = sin^2(pi t / (2 T_r)) for t < T_r
+__device__ __forceinline__ double field_time_factor(int mode, double t, double omega, double t_ramp, double ramp_k)
+{
+    if (mode != QW_BEAM_STANDING_PARAXIAL_) return 1.0;
+    double f = 1.0, s, c;
+    if (t_ramp > 0.0 && t < t_ramp) {
+        sincos_phase(ramp_k * t, s, c);
+        f = s * s;
+    }
+    sincos_phase(omega * t, s, c);
+    return f * c;
+}
+
+// cos(th) and sin(th)/|A| = (c tau) sin(th)/th for th = c |A| tau; the series
+// below the threshold also covers |A| = 0 exactly.
+__device__ __forceinline__ void cos_sinc(float th, float ctau, float amag, float& C, float& S)
+{
+    if (fabsf(th) < 1e-2f) {
+        float t2 = th * th;
+        C = 1.0f - t2 * (0.5f - t2 * (1.0f / 24.0f));
+        S = ctau * (1.0f - t2 * (1.0f / 6.0f - t2 * (1.0f / 120.0f)));
+    } else {
+        float sn, cs;
+        sincos_phase((double)th, sn, cs);
+        C = cs;
+        S = sn / amag;
+    }
+}
+__device__ __forceinline__ void cos_sinc(double th, double ctau, double amag, double& C, double& S)
+{
+    if (fabs(th) < 1e-4) {
+        double t2 = th * th;
+        C = 1.0 - t2 * (0.5 - t2 * (1.0 / 24.0));
+        S = ctau * (1.0 - t2 * (1.0 / 6.0 - t2 * (1.0 / 120.0)));
+    } else {
+        double sn, cs;
+        sincos_phase(th, sn, cs);
+        C = cs;
+        S = sn / amag;
+    }
+}
+
+// the kinetic phase E dt is formed in double and reduced in double; the
+// float form evaluates sin/cos of the reduced argument in float
+template <typename T>
+__device__ __forceinline__ void phase_sincos(double ph, T& s, T& c)
+{
+    sincos_phase(ph, s, c);
+}
+
+__device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k : k - n; }
+
+// ---------------------------------------------------------------------------
+// row pass
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE))) void row_pass(RowArgs a)
+{
+    using S = shape<T, N>;
+    constexpr int E = S::E, NT = S::NT, L = S::L, RPW = S::RPW, LL = S::LL;
+    __shared__ cx<T> lds[RPW * 2 * LL];
+    const int blk = threadIdx.x & 1;  // 0: (psi1, psi4), 1: (psi2, psi3)
+    const int q = threadIdx.x >> 1;
+    const int s = q / NT;
+    const int t = q - s * NT;
+    const int y = blockIdx.x * RPW + s;
+    const bool live = y < a.ny;
+    cx<T>* lb = lds + (2 * s + blk) * LL;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twx);
+    // byte offsets: lane (y, t, block) plus m NT cells per element; a
+    // non-live row is pointed past the array (reads zero, writes dropped)
+    constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
+    const uint32_t bytes = (uint32_t)a.ny * N * CB;
+    const uint32_t lane = live ? ((uint32_t)y * N + t) * CB : bytes;
+    const uint32_t o0 = lane + (blk ? 1u : 0u) * sizeof(cx<T>), o1 = lane + (blk ? 2u : 3u) * sizeof(cx<T>);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, bytes);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, bytes);
+
+    cx<T> v[2][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        v[0][m] = bload((cx<T>*)nullptr, rs, o0, m * NT * CB);
+        v[1][m] = bload((cx<T>*)nullptr, rs, o1, m * NT * CB);
+    }
+
+    if constexpr (MODE == ROW_FWD_NORM) {
+        // sum |psi|^2 of this row in double (fixed tree over the row's lanes)
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                acc += (double)v[c][m].re * (double)v[c][m].re + (double)v[c][m].im * (double)v[c][m].im;
+        double* red = reinterpret_cast<double*>(lds);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        const int l = threadIdx.x - s * L;
+        for (int w = L / 2; w > 0; w >>= 1) {
+            if (l < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (l == 0 && live) a.rownorm[y] = red[threadIdx.x];
+        __syncthreads();
+    }
+
+    if constexpr (MODE == ROW_MID || MODE == ROW_LAST || MODE == ROW_INV_SCALE)
+        fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
+
+    if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_LAST) {
+        // interaction propagator V(t, tau) with A evaluated from the field tables
+        const double tk = a.t0 + (double)a.k * a.dt;
+        const T sfac = (T)field_time_factor(a.beam_mode, tk, a.omega, a.t_ramp, a.ramp_k);
+        const T tau = (T)(a.tau_frac * a.dt);
+        const T c = (T)a.c;
+        const cx<T>* bxt = reinterpret_cast<const cx<T>*>(a.beam_x);
+        const cx<T> yb = reinterpret_cast<const cx<T>*>(a.beam_y)[live ? y : 0];
+        const T ay_row = sfac * yb.re, ax_row = sfac * yb.im;
+        const T sgn = blk ? (T)-1 : (T)1;
+        asm volatile("" ::: "memory");  // table loads stay here, not in the transform above
+        int tt = t;
+        asm volatile("" : "+v"(tt));
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const cx<T> xb = bxt[tt + NT * m];
+            const T ax = ax_row * xb.im, ay = ay_row * xb.re;
+            const T amag = sqrt(ax * ax + ay * ay);
+            T C, Sn;
+            cos_sinc(c * amag * tau, c * tau, amag, C, Sn);
+            block_prop(v[0][m], v[1][m], C, (T)0, Sn * ax, sgn * Sn * ay);
+        }
+    }
+
+    if constexpr (MODE == ROW_INV_SCALE) {
+        // normalise the initial packet: sum |psi|^2 = nx ny sum |phi|^2
+        const T sc = (T)(1.0 / sqrt(a.scale_src[0] * (double)N * (double)a.ny));
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) v[c][m] = scale(v[c][m], sc);
+    }
+
+    if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_FWD_NORM)
+        fft<T, N, E, 2, false>(typename plan<T, N>::S{}, v, t, tw, lb);
+
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        bstore(v[0][m], rd, o0, m * NT * CB);
+        bstore(v[1][m], rd, o1, m * NT * CB);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// column pass
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE))) void col_pass(ColArgs a)
+{
+    using S = shape<T, N>;
+    constexpr int E = S::E, NT = S::NT, TX = S::TX, LL = S::LL;
+    __shared__ cx<T> lds[TX * 2 * LL];
+    // lane order: block fastest, then the column within the tile, then t, so
+    // a wave reads TX whole cells of each of several rows
+    const int blk = threadIdx.x & 1;
+    const int cl = (threadIdx.x >> 1) % TX;
+    const int t = (threadIdx.x >> 1) / TX;
+    const int x = blockIdx.x * TX + cl;
+    const bool live = x < a.nx;
+    cx<T>* lb = lds + (2 * cl + blk) * LL;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twy);
+    constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
+    const uint32_t bytes = (uint32_t)a.nx * N * CB;
+    const uint32_t lane = live ? ((uint32_t)t * a.nx + x) * CB : bytes;
+    const uint32_t o0 = lane + (blk ? 1u : 0u) * sizeof(cx<T>), o1 = lane + (blk ? 2u : 3u) * sizeof(cx<T>);
+    const uint32_t mstride = (uint32_t)NT * a.nx * CB;  // bytes between a lane's elements
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(a.psi, bytes);
+
+    cx<T> v[2][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        v[0][m] = bload((cx<T>*)nullptr, rp, o0, m * mstride);
+        v[1][m] = bload((cx<T>*)nullptr, rp, o1, m * mstride);
+    }
+
+    if constexpr (MODE == COL_INV) {
+        fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
+    } else {
+        fft<T, N, E, 2, false>(typename plan<T, N>::S{}, v, t, tw, lb);
+    }
+
+    const double c = a.c;
+    const int kxs = signed_idx(live ? x : 0, a.nx);
+    const double px = a.dkx * (double)kxs;
+
+    if constexpr (MODE == COL_PROP) {
+        // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny)
+        const T nrm = (T)a.inv_cells;
+        const T cT = (T)c;
+        const T sgn = blk ? (T)-1 : (T)1;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int kys = signed_idx(t + NT * m, N);
+            const double py = a.dky * (double)kys;
+            const double en = c * sqrt(c * c + px * px + py * py);
+            T sn, cs;
+            phase_sincos(en * a.dt, sn, cs);
+            const T se = sn / (T)en * nrm;  // sin(E dt)/(E nx ny)
+            block_prop(v[0][m], v[1][m], cs * nrm, se * cT * cT, se * cT * (T)px, sgn * se * cT * (T)py);
+        }
+        fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
+    }
+
+    if constexpr (MODE == COL_PROP || MODE == COL_INV) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            bstore(v[0][m], rp, o0, m * mstride);
+            bstore(v[1][m], rp, o1, m * mstride);
+        }
+    }
+
+    if constexpr (MODE == COL_OBS) {
+        // spin projections onto the unit bispinors u^+-(p) (Eq. 9, 18):
+        //   c^s = sqrt((E + c^2)/(2E)) (aA + s aB)/sqrt2,
+        //   aA = phi1 + k (px - i py) phi4,  aB = phi2 + k (px + i py) phi3,  k = c/(E + c^2)
+        // Block A lanes hold (phi1, phi4), block B lanes (phi2, phi3); the
+        // partner lane's value comes by a lane shuffle.
+        double sw = 0.0, sp = 0.0, sm = 0.0;
+        const double sg = blk ? -1.0 : 1.0;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int kys = signed_idx(t + NT * m, N);
+            const double py = a.dky * (double)kys;
+            const double en = c * sqrt(c * c + px * px + py * py);
+            const double kk = c / (en + c * c);
+            const double tr = v[0][m].re, ti = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
+            // top + k (px - i sg py) bot
+            const double ar = tr + kk * (px * br + sg * py * bi), ai = ti + kk * (px * bi - sg * py * br);
+            const double or_ = __shfl_xor(ar, 1), oi = __shfl_xor(ai, 1);
+            if (live) {
+                sw += tr * tr + ti * ti + br * br + bi * bi;
+                if (blk == 0) {
+                    const double nn = (en + c * c) / (4.0 * en);
+                    const double pr = ar + or_, pi = ai + oi, mr = ar - or_, mi = ai - oi;
+                    sp += nn * (pr * pr + pi * pi);
+                    sm += nn * (mr * mr + mi * mi);
+                }
+            }
+        }
+        __syncthreads();  // LDS reused for the reduction
+        double* red = reinterpret_cast<double*>(lds);
+        constexpr int nthr = TX * S::L;
+        red[threadIdx.x] = sw;
+        red[nthr + threadIdx.x] = sp;
+        red[2 * nthr + threadIdx.x] = sm;
+        __syncthreads();
+        // fold the lanes of each column (index = (t TX + cl) 2 + blk) onto t = 0, blk = 0
+        for (int w = nthr / 2; w >= 2 * TX; w >>= 1) {
+            if (threadIdx.x < w) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) red[q * nthr + threadIdx.x] += red[q * nthr + threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int nb = 2 * a.n_max + 1;
+            double* out = a.partial + (size_t)blockIdx.x * a.partial_stride;
+            for (int i = 0; i < 3 * nb + 3; ++i) out[i] = 0.0;
+            for (int qc = 0; qc < TX; ++qc) {
+                const int xq = blockIdx.x * TX + qc;
+                if (xq >= a.nx) break;
+                const double w = red[2 * qc] + red[2 * qc + 1];
+                const double wp = red[nthr + 2 * qc], wm = red[2 * nthr + 2 * qc];
+                const int ks = signed_idx(xq, a.nx);
+                // nearest order centre, then the window test
+                const int d0 = ks - a.band_ref + a.band_half;
+                const int twom = 2 * a.band_half;
+                const int n = d0 >= 0 ? d0 / twom : -((-d0 + twom - 1) / twom);
+                int dd = ks - a.band_ref - twom * n;
+                dd = dd < 0 ? -dd : dd;
+                if (dd <= a.window && n >= -a.n_max && n <= a.n_max) {
+                    out[n + a.n_max] += w;
+                    out[nb + n + a.n_max] += wp;
+                    out[2 * nb + n + a.n_max] += wm;
+                }
+                out[3 * nb] += w;
+                out[3 * nb + 1] += (a.spin0 >= 0 ? wm : wp);
+                out[3 * nb + 2] += wp + wm;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tables
+// ---------------------------------------------------------------------------
+// twiddles exp(-2 pi i k / n), k < n, evaluated in double
+template <typename T>
+__global__ void twiddle_table(cx<T>* tw, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double s, c;
+    sincospi(2.0 * (double)k / (double)n, &s, &c);
+    tw[k] = cx<T>{(T)c, (T)-s};
+}
+
+// field tables: beam_x[i] = (X0, X1) and beam_y[j] = (Y0, Y1) with
+// A_y = s(t) Y0(y) X0(x), A_x = s(t) Y1(y) X1(x)
+template <typename T>
+__global__ void beam_tables(cx<T>* bx, cx<T>* by, BeamArgs b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < b.nx) {
+        T x0 = 1, x1 = 1;
+        if (b.mode == QW_BEAM_STANDING_PARAXIAL_) {
+            const double x = b.x_min + b.lx * (double)i / (double)b.nx;
+            x0 = (T)cos(b.kl * x);
+            x1 = (T)sin(b.kl * x);
+        }
+        bx[i] = cx<T>{x0, x1};
+    }
+    if (i < b.ny) {
+        T y0 = 0, y1 = 0;
+        if (b.mode == QW_BEAM_STANDING_PARAXIAL_) {
+            const double y = b.y_min + b.ly * (double)i / (double)b.ny;
+            const double env = exp(-(y * y) / (b.w0 * b.w0));
+            y0 = (T)(b.a0 * env);
+            y1 = b.longitudinal ? (T)(b.a0 * (2.0 * y / (b.kl * b.w0 * b.w0)) * env) : (T)0;
+        } else if (b.mode == QW_BEAM_UNIFORM_) {
+            y0 = (T)b.uy;
+            y1 = (T)b.ux;
+        }
+        by[i] = cx<T>{y0, y1};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial packet in momentum space: phi(p) = g(p) u^s(p) exp(i p.(r_min - r0)),
+// one workgroup per momentum row ky; row sums of |phi|^2 to rownorm[ky]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void packet_momentum(cx<T>* psi, double* rownorm, PacketArgs e)
+{
+    __shared__ double red[256];
+    const int ky = blockIdx.x;
+    const double c = e.c;
+    const double py = e.dky * (double)signed_idx(ky, e.ny);
+    const double sp = 1.0 / (2.0 * e.sigma_x);
+    const double r2 = 0.70710678118654752440;
+    const double chi1 = r2, chi2 = e.spin >= 0 ? r2 : -r2;
+    double acc = 0.0;
+    for (int kx = threadIdx.x; kx < e.nx; kx += blockDim.x) {
+        const double px = e.dkx * (double)signed_idx(kx, e.nx);
+        const double dx = px - e.p0x, dy = py - e.p0y;
+        const double amp = exp(-(dx * dx + dy * dy) / (4.0 * sp * sp));
+        const double en = c * sqrt(c * c + px * px + py * py);
+        const double nrm = sqrt((en + c * c) / (2.0 * en));
+        const double kk = c / (en + c * c);
+        double sn, cs;
+        sincos(px * (e.x_min - e.x0) + py * (e.y_min - e.y0), &sn, &cs);
+        // u = nrm (chi1, chi2, k (px - i py) chi2, k (px + i py) chi1)
+        const double u1 = nrm * chi1, u2 = nrm * chi2;
+        const double u3r = nrm * kk * px * chi2, u3i = -nrm * kk * py * chi2;
+        const double u4r = nrm * kk * px * chi1, u4i = nrm * kk * py * chi1;
+        const double ar = amp * cs, ai = amp * sn;
+        cx<T>* q = psi + ((size_t)ky * e.nx + kx) * 4;
+        q[0] = cx<T>{(T)(u1 * ar), (T)(u1 * ai)};
+        q[1] = cx<T>{(T)(u2 * ar), (T)(u2 * ai)};
+        q[2] = cx<T>{(T)(u3r * ar - u3i * ai), (T)(u3r * ai + u3i * ar)};
+        q[3] = cx<T>{(T)(u4r * ar - u4i * ai), (T)(u4r * ai + u4i * ar)};
+        acc += amp * amp;  // |u| = 1
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rownorm[ky] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host side)
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+hipError_t row_launch_n(int mode, const RowArgs& a, hipStream_t st)
+{
+    using S = shape<T, N>;
+    const dim3 grid((a.ny + S::RPW - 1) / S::RPW), block(S::RPW * S::L);
+    switch (mode) {
+    case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST>), grid, block, 0, st, a); break;
+    case ROW_MID: hipLaunchKernelGGL((row_pass<T, N, ROW_MID>), grid, block, 0, st, a); break;
+    case ROW_LAST: hipLaunchKernelGGL((row_pass<T, N, ROW_LAST>), grid, block, 0, st, a); break;
+    case ROW_FWD_NORM: hipLaunchKernelGGL((row_pass<T, N, ROW_FWD_NORM>), grid, block, 0, st, a); break;
+    case ROW_INV_SCALE: hipLaunchKernelGGL((row_pass<T, N, ROW_INV_SCALE>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t col_launch_n(int mode, const ColArgs& a, hipStream_t st)
+{
+    using S = shape<T, N>;
+    const dim3 grid((a.nx + S::TX - 1) / S::TX), block(S::TX * S::L);
+    switch (mode) {
+    case COL_PROP: hipLaunchKernelGGL((col_pass<T, N, COL_PROP>), grid, block, 0, st, a); break;
+    case COL_INV: hipLaunchKernelGGL((col_pass<T, N, COL_INV>), grid, block, 0, st, a); break;
+    case COL_OBS: hipLaunchKernelGGL((col_pass<T, N, COL_OBS>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+#define QW_SIZE_SWITCH(n, CALL)        \
+    switch (n) {                       \
+    case 8: return CALL(8);            \
+    case 16: return CALL(16);          \
+    case 32: return CALL(32);          \
+    case 64: return CALL(64);          \
+    case 128: return CALL(128);        \
+    case 256: return CALL(256);        \
+    case 512: return CALL(512);        \
+    case 1024: return CALL(1024);      \
+    case 2048: return CALL(2048);      \
+    case 4096: return CALL(4096);      \
+    default: break;                    \
+    }
+
+template <typename T>
+hipError_t launch_row(int mode, int nx, const RowArgs& a, hipStream_t st)
+{
+#define QW_CALL(NN) row_launch_n<T, NN>(mode, a, st)
+    QW_SIZE_SWITCH(nx, QW_CALL)
+#undef QW_CALL
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_col(int mode, int ny, const ColArgs& a, hipStream_t st)
+{
+#define QW_CALL(NN) col_launch_n<T, NN>(mode, a, st)
+    QW_SIZE_SWITCH(ny, QW_CALL)
+#undef QW_CALL
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+int col_blocks(int nx, int ny)
+{
+#define QW_CALL(NN) (nx + shape<T, NN>::TX - 1) / shape<T, NN>::TX
+    QW_SIZE_SWITCH(ny, QW_CALL)
+#undef QW_CALL
+    return -1;
+}
+#undef QW_SIZE_SWITCH
+
+template <typename T>
+hipError_t launch_twiddles(void* tw, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(twiddle_table<T>, dim3((n + 255) / 256), dim3(256), 0, st, reinterpret_cast<cx<T>*>(tw), n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_beam_tables(void* bx, void* by, const BeamArgs& b, hipStream_t st)
+{
+    const int n = b.nx > b.ny ? b.nx : b.ny;
+    hipLaunchKernelGGL(beam_tables<T>, dim3((n + 255) / 256), dim3(256), 0, st, reinterpret_cast<cx<T>*>(bx),
+                       reinterpret_cast<cx<T>*>(by), b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_packet(void* psi, double* rownorm, const PacketArgs& e, hipStream_t st)
+{
+    hipLaunchKernelGGL(packet_momentum<T>, dim3(e.ny), dim3(256), 0, st, reinterpret_cast<cx<T>*>(psi), rownorm, e);
+    return hipGetLastError();
+}
+
+}  // namespace qw
+
+#define QW_DEFINE_LAUNCHERS(T, SUF)                                                                           \
+    namespace qw {                                                                                           \
+    hipError_t launch_row_##SUF(int mode, int nx, const RowArgs& a, hipStream_t s)                          \
+    {                                                                                                        \
+        return launch_row<T>(mode, nx, a, s);                                                                \
+    }                                                                                                        \
+    hipError_t launch_col_##SUF(int mode, int ny, const ColArgs& a, hipStream_t s)                          \
+    {                                                                                                        \
+        return launch_col<T>(mode, ny, a, s);                                                                \
+    }                                                                                                        \
+    int col_blocks_##SUF(int nx, int ny) { return col_blocks<T>(nx, ny); }                                   \
+    hipError_t launch_twiddles_##SUF(void* tw, int n, hipStream_t s) { return launch_twiddles<T>(tw, n, s); } \
+    hipError_t launch_beam_tables_##SUF(void* bx, void* by, const BeamArgs& b, hipStream_t s)               \
+    {                                                                                                        \
+        return launch_beam_tables<T>(bx, by, b, s);                                                          \
+    }                                                                                                        \
+    hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s)          \
+    {                                                                                                        \
+        return launch_packet<T>(psi, rownorm, e, s);                                                         \
+    }                                                                                                        \
+    }

@@ -1,0 +1,228 @@
+"""ctypes binding of libqw.so (include/qw.h) -- argument marshalling only.
+
+The functions below carry the C names and forward to the library; every
+step of the computation runs in the library's HIP kernels.  There is no
+fallback: if libqw.so is missing or cannot be loaded, ``lib()`` raises.
+
+``Sim`` is a convenience owner of the torch tensors (state and workspace) on
+one device; torch is used only as the device allocator and for streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import asdict
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqw.so")
+
+QW_OK = 0
+QW_E_ARG = -1
+QW_E_SIZE = -2
+QW_E_WORKSPACE = -3
+QW_E_DEVICE = -4
+QW_E_NUMERIC = -5
+QW_E_STATE = -6
+
+QW_F64 = 0
+QW_F32 = 1
+
+QW_BEAM_NONE = 0
+QW_BEAM_STANDING_PARAXIAL = 1
+QW_BEAM_UNIFORM = 2
+
+EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_init_packet", "qw_step_n",
+            "qw_observables", "qw_kernel_timing", "qw_kernel_times", "qw_last_error", "qw_destroy")
+
+
+class qw_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x_min", ctypes.c_double), ("y_min", ctypes.c_double),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("c", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class qw_beam(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("a0", ctypes.c_double), ("lambda_l", ctypes.c_double),
+                ("w0", ctypes.c_double), ("ramp_periods", ctypes.c_double),
+                ("longitudinal", ctypes.c_int32), ("ux", ctypes.c_double), ("uy", ctypes.c_double)]
+
+
+class qw_packet(ctypes.Structure):
+    _fields_ = [("p0x", ctypes.c_double), ("p0y", ctypes.c_double), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("sigma_x", ctypes.c_double), ("spin", ctypes.c_int32)]
+
+
+class qw_obs_spec(ctypes.Structure):
+    _fields_ = [("band_ref_idx", ctypes.c_int32), ("band_half_idx", ctypes.c_int32),
+                ("window_idx", ctypes.c_int32), ("n_max", ctypes.c_int32), ("spin0", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libqw.so (built by ``paper_2307_01571_amd.build``); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_01571_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.qw_workspace_bytes.argtypes = [ctypes.POINTER(qw_grid), ctypes.POINTER(ctypes.c_size_t)]
+    L.qw_init_grid.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(qw_grid), vp, ctypes.c_size_t, vp]
+    L.qw_set_beam.argtypes = [vp, ctypes.POINTER(qw_beam)]
+    L.qw_init_packet.argtypes = [vp, vp, ctypes.POINTER(qw_packet), vp]
+    L.qw_step_n.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, vp]
+    L.qw_observables.argtypes = [vp, vp, ctypes.POINTER(qw_obs_spec), dp, ctypes.c_int32, vp]
+    L.qw_kernel_timing.argtypes = [vp, ctypes.c_int]
+    L.qw_kernel_times.argtypes = [vp, dp, ctypes.c_int32, vp]
+    L.qw_last_error.argtypes = [vp]
+    L.qw_last_error.restype = ctypes.c_char_p
+    L.qw_destroy.argtypes = [vp]
+    L.qw_destroy.restype = None
+    for name in EXPORTED:
+        if name not in ("qw_last_error", "qw_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class QWError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qw status {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, ctx=None):
+    if rc != QW_OK:
+        raise QWError(rc, qw_last_error(ctx))
+
+
+# ---- C names, marshalling only -------------------------------------------
+def qw_workspace_bytes(grid: qw_grid) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().qw_workspace_bytes(ctypes.byref(grid), ctypes.byref(n)))
+    return n.value
+
+
+def qw_init_grid(grid: qw_grid, workspace_ptr: int, ws_bytes: int, stream: int) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().qw_init_grid(ctypes.byref(h), ctypes.byref(grid), ctypes.c_void_p(workspace_ptr),
+                              ws_bytes, ctypes.c_void_p(stream)))
+    return h.value
+
+
+def qw_set_beam(ctx: int, beam: qw_beam) -> None:
+    _check(lib().qw_set_beam(ctypes.c_void_p(ctx), ctypes.byref(beam)), ctx)
+
+
+def qw_init_packet(ctx: int, psi_ptr: int, packet: qw_packet, stream: int) -> None:
+    _check(lib().qw_init_packet(ctypes.c_void_p(ctx), ctypes.c_void_p(psi_ptr), ctypes.byref(packet),
+                                ctypes.c_void_p(stream)), ctx)
+
+
+def qw_step_n(ctx: int, psi_ptr: int, n: int, t0: float, dt: float, stream: int) -> None:
+    _check(lib().qw_step_n(ctypes.c_void_p(ctx), ctypes.c_void_p(psi_ptr), int(n), float(t0), float(dt),
+                           ctypes.c_void_p(stream)), ctx)
+
+
+def qw_observables(ctx: int, psi_ptr: int, spec: qw_obs_spec, stream: int, check: bool = True):
+    nb = 2 * spec.n_max + 1
+    out = (ctypes.c_double * (3 * nb + 3))()
+    rc = lib().qw_observables(ctypes.c_void_p(ctx), ctypes.c_void_p(psi_ptr), ctypes.byref(spec), out,
+                              3 * nb + 3, ctypes.c_void_p(stream))
+    if check:
+        _check(rc, ctx)
+    return rc, [float(v) for v in out]
+
+
+def qw_kernel_timing(ctx: int, enable: bool) -> None:
+    _check(lib().qw_kernel_timing(ctypes.c_void_p(ctx), int(bool(enable))), ctx)
+
+
+def qw_kernel_times(ctx: int, stream: int):
+    out = (ctypes.c_double * 4)()
+    _check(lib().qw_kernel_times(ctypes.c_void_p(ctx), out, 4, ctypes.c_void_p(stream)), ctx)
+    return [float(v) for v in out]
+
+
+def qw_last_error(ctx=None) -> str:
+    s = lib().qw_last_error(ctypes.c_void_p(ctx) if ctx else None)
+    return s.decode() if s else ""
+
+
+def qw_destroy(ctx: int) -> None:
+    lib().qw_destroy(ctypes.c_void_p(ctx))
+
+
+# ---- convenience owner of device tensors ---------------------------------
+def unpack_observables(out, n_max: int) -> dict:
+    nb = 2 * n_max + 1
+    return {"norm": out[0], "P": list(out[1:1 + nb]), "Pp": list(out[1 + nb:1 + 2 * nb]),
+            "Pm": list(out[1 + 2 * nb:1 + 3 * nb]), "P_flip": out[1 + 3 * nb], "P_neg": out[2 + 3 * nb]}
+
+
+class Sim:
+    """State and workspace tensors for one grid on one device, plus its context.
+
+    grid/beam/packet/obs are the dataclasses of ``workloads`` (or anything with
+    the same fields).  ``psi`` is a (ny, nx, 4) complex64/complex128 tensor.
+    """
+
+    def __init__(self, grid, precision: int = QW_F64, device: str = "cuda:0", beam=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.g = qw_grid(grid.nx, grid.ny, grid.x_min, grid.y_min, grid.lx, grid.ly, grid.c, precision)
+        self.dtype = torch.complex64 if precision == QW_F32 else torch.complex128
+        nbytes = qw_workspace_bytes(self.g)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.psi = torch.zeros((grid.ny, grid.nx, 4), dtype=self.dtype, device=self.device)
+        self.ctx = qw_init_grid(self.g, self.ws.data_ptr(), nbytes, self.stream())
+        if beam is not None:
+            self.set_beam(beam)
+
+    def stream(self) -> int:
+        with self.torch.cuda.device(self.device):
+            return self.torch.cuda.current_stream().cuda_stream
+
+    def set_beam(self, b) -> None:
+        qw_set_beam(self.ctx, qw_beam(b.mode, b.a0, b.lambda_l, b.w0, b.ramp_periods, b.longitudinal, b.ux, b.uy))
+
+    def init_packet(self, p) -> None:
+        qw_init_packet(self.ctx, self.psi.data_ptr(),
+                       qw_packet(p.p0x, p.p0y, p.x0, p.y0, p.sigma_x, p.spin), self.stream())
+
+    def load(self, psi_host) -> None:
+        """Copy a (ny, nx, 4) host array into the device state."""
+        t = self.torch.as_tensor(psi_host).to(self.dtype)
+        self.psi.copy_(t.to(self.device))
+
+    def step(self, n: int, t0: float, dt: float) -> None:
+        qw_step_n(self.ctx, self.psi.data_ptr(), n, t0, dt, self.stream())
+
+    def observables(self, o, check: bool = True):
+        spec = qw_obs_spec(o.band_ref_idx, o.band_half_idx, o.window_idx, o.n_max, o.spin0)
+        rc, out = qw_observables(self.ctx, self.psi.data_ptr(), spec, self.stream(), check=check)
+        return out if check else (rc, out)
+
+    def state(self):
+        """Host copy of psi as a numpy complex128 array."""
+        self.torch.cuda.synchronize(self.device)
+        return self.psi.detach().cpu().to(self.torch.complex128).numpy()
+
+    def close(self) -> None:
+        if self.ctx:
+            qw_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

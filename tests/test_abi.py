@@ -1,0 +1,101 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/qw.h declares, and rejects bad arguments on the host before
+anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2307_01571_amd import qw
+from paper_2307_01571_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qw.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qw_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("qw_init_grid", "qw_set_beam", "qw_step_n", "qw_observables", "qw_init_packet",
+                 "qw_workspace_bytes", "qw_last_error", "qw_destroy"):
+        assert must in names
+    assert set(names) == set(qw.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = qw.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+        assert ctypes.cast(getattr(L, name), ctypes.c_void_p).value
+
+
+def grid(n=64, prec=qw.QW_F64, nx=None, ny=None):
+    g = W.square_box(n, 16)
+    return qw.qw_grid(g.nx if nx is None else nx, g.ny if ny is None else ny, g.x_min, g.y_min, g.lx, g.ly, g.c,
+                      prec)
+
+
+def test_workspace_bytes_is_host_only_and_scales():
+    b64 = qw.qw_workspace_bytes(grid(64))
+    b64f = qw.qw_workspace_bytes(grid(64, qw.QW_F32))
+    b128 = qw.qw_workspace_bytes(grid(128))
+    # one state-sized plane dominates: 64*64*4 complex
+    assert b64 >= 64 * 64 * 4 * 16 and b64f >= 64 * 64 * 4 * 8
+    assert b128 > 3 * b64
+    assert b64 % 256 == 0
+
+
+@pytest.mark.parametrize("nx,ny", [(4, 64), (64, 4), (48, 64), (8192, 8), (0, 8), (-8, 8)])
+def test_bad_sizes_are_rejected(nx, ny):
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_workspace_bytes(grid(nx=nx, ny=ny))
+    assert e.value.code == qw.QW_E_SIZE
+    assert "power of two" in qw.qw_last_error(None)
+
+
+def test_bad_grid_values_are_rejected():
+    g = grid()
+    g.lx = -1.0
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_workspace_bytes(g)
+    assert e.value.code == qw.QW_E_ARG
+    g = grid()
+    g.precision = 7
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_workspace_bytes(g)
+    assert e.value.code == qw.QW_E_ARG
+    g = grid()
+    g.c = float("nan")
+    with pytest.raises(qw.QWError):
+        qw.qw_workspace_bytes(g)
+
+
+def test_init_grid_rejects_null_and_short_workspace_before_any_device_call():
+    L = qw.lib()
+    h = ctypes.c_void_p()
+    g = grid()
+    assert L.qw_init_grid(ctypes.byref(h), ctypes.byref(g), None, 1 << 20, None) == qw.QW_E_ARG
+    assert h.value is None
+    # a misaligned pointer and a too-small size are caught from the numbers alone
+    assert L.qw_init_grid(ctypes.byref(h), ctypes.byref(g), ctypes.c_void_p(0x1001), 1 << 30, None) == \
+        qw.QW_E_WORKSPACE
+    assert L.qw_init_grid(ctypes.byref(h), ctypes.byref(g), ctypes.c_void_p(0x1000), 16, None) == \
+        qw.QW_E_WORKSPACE
+    assert "workspace" in qw.qw_last_error(None)
+    assert L.qw_init_grid(None, ctypes.byref(g), None, 0, None) == qw.QW_E_ARG
+
+
+def test_calls_on_null_context_fail_cleanly():
+    L = qw.lib()
+    b = qw.qw_beam(qw.QW_BEAM_NONE, 0, 0.5, 1, 0, 0, 0, 0)
+    assert L.qw_set_beam(None, ctypes.byref(b)) == qw.QW_E_ARG
+    assert L.qw_step_n(None, None, 1, 0.0, 1.0, None) == qw.QW_E_ARG
+    out = (ctypes.c_double * 8)()
+    assert L.qw_kernel_times(None, out, 8, None) == qw.QW_E_ARG
+    L.qw_destroy(None)
