@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the split-operator step on one MI355X.
+
+One bench step is one full Strang step (row pass + column pass) of the
+2048 x 2048 FP32 workload (box 64 lambda, w0 = 16 lambda, A0 = 0.5, Gaussian
+packet at p = (-k_L, 0.1 k_L)).  By default the timed region is the whole
+5e4-step propagation, run as one qw_step_n call with the state resident in
+HBM.  Afterwards, untimed:
+  * the same propagation in FP64, whose band and spin probabilities the FP32
+    result is compared with (max absolute error);
+  * a shorter run with per-launch HIP events, giving the average duration of
+    each pass and its fraction of the HBM roofline;
+  * the oracle (FP64 CPU) on a bounded sample of the same workload.
+Prints one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--gpus 1] [--steps 50000] [--warmup 500]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_CELL_PASS = {"f32": 64, "f64": 128}  # read + write of 4 complex per pass
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def run_precision(qw, wl, prec, steps, warmup, torch):
+    sim = qw.Sim(wl.grid, prec, beam=wl.beam)
+    if warmup:
+        sim.init_packet(wl.packet)
+        sim.step(warmup, 0.0, wl.dt)
+    sim.init_packet(wl.packet)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, 0.0, wl.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    obs = sim.observables(wl.obs)
+    return sim, elapsed, obs
+
+
+def kernel_times(qw, sim, wl, steps, torch):
+    sim.init_packet(wl.packet)
+    torch.cuda.synchronize()
+    qw.qw_kernel_timing(sim.ctx, True)
+    sim.step(steps, 0.0, wl.dt)
+    cnt_r, ms_r, cnt_c, ms_c = qw.qw_kernel_times(sim.ctx, sim.stream())
+    qw.qw_kernel_timing(sim.ctx, False)
+    return {"row": (cnt_r, ms_r), "col": (cnt_c, ms_c)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50_000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--timing-steps", type=int, default=2000)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
+                         "128 MiB written), the reference for bandwidth and traffic counters")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the workload does not "
+              "shard across GPUs in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2307_01571_amd import qw
+    from paper_2307_01571_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    qw.lib()
+    wl = W.large()
+    cells = wl.grid.nx * wl.grid.ny
+
+    if a.copy_probe:
+        src = torch.empty((wl.grid.ny, wl.grid.nx, 4), dtype=torch.complex64, device="cuda")
+        src.real.fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        n = 50
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(n):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / n
+        nbytes = 2 * src.numel() * src.element_size()
+        print(json.dumps({"probe": "torch copy", "bytes_read": nbytes // 2, "bytes_written": nbytes // 2,
+                          "avg_us": us, "GBps": nbytes / (us * 1e-6) / 1e9}), flush=True)
+        return
+
+    log(f"FP32 {wl.grid.nx}x{wl.grid.ny}: warmup {a.warmup}, timed {a.steps} steps")
+    sim32, t32, obs32 = run_precision(qw, wl, qw.QW_F32, a.steps, a.warmup, torch)
+    value = cells * a.steps / t32
+    log(f"FP32: {t32:.3f} s, {value:.4e} cell-steps/s, {1e3 * t32 / a.steps:.4f} ms/step")
+
+    kt = kernel_times(qw, sim32, wl, min(a.timing_steps, a.steps), torch)
+    per = {}
+    for k, (cnt, ms) in kt.items():
+        avg_s = ms / max(cnt, 1) / 1e3
+        gbs = BYTES_PER_CELL_PASS["f32"] * cells / avg_s / 1e9
+        per[k] = {"launches": int(cnt), "avg_us": avg_s * 1e6, "GBps": gbs}
+        log(f"  {k} pass: {cnt:.0f} launches, avg {avg_s * 1e6:.2f} us, {gbs:.0f} GB/s algorithmic")
+    dom = max(per, key=lambda k: per[k]["avg_us"])
+    roofline = {"bound": "hbm", "kernel": "col_pass" if dom == "col" else "row_pass",
+                "achieved": round(per[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(per[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": BYTES_PER_CELL_PASS["f32"] * cells,
+                "avg_launch_us": {k: round(v["avg_us"], 3) for k, v in per.items()},
+                "step_GBps": round(2 * BYTES_PER_CELL_PASS["f32"] * cells * a.steps / t32 / 1e9, 1)}
+    sim32.close()
+
+    extra = {}
+    if not a.no_f64:
+        log(f"FP64 reference run, {a.steps} steps")
+        sim64, t64, obs64 = run_precision(qw, wl, qw.QW_F64, a.steps, 0, torch)
+        sim64.close()
+        o32 = qw.unpack_observables(obs32, wl.obs.n_max)
+        o64 = qw.unpack_observables(obs64, wl.obs.n_max)
+        err = {}
+        for key in ("P", "Pp", "Pm"):
+            err[key] = float(np.max(np.abs(np.array(o32[key]) - np.array(o64[key]))))
+        err["P_flip"] = abs(o32["P_flip"] - o64["P_flip"])
+        err["P_flip_rel"] = err["P_flip"] / max(abs(o64["P_flip"]), 1e-300)
+        err["P_neg"] = abs(o32["P_neg"] - o64["P_neg"])
+        err["norm_drift_f32"] = o32["norm"] - 1.0
+        err["max_abs_prob"] = max(err["P"], err["Pp"], err["Pm"], err["P_flip"])
+        extra["f64"] = {"value": cells * a.steps / t64, "ms_per_step": 1e3 * t64 / a.steps,
+                        "speedup_f32_over_f64": t64 / t32}
+        extra["accuracy_vs_f64"] = err
+        extra["probabilities_f64"] = {"P": o64["P"], "Pp": o64["Pp"], "Pm": o64["Pm"],
+                                      "P_flip": o64["P_flip"], "P_neg": o64["P_neg"]}
+        log(f"FP64: {t64:.3f} s; FP32 max |dP| = {err['max_abs_prob']:.3e}")
+
+    # oracle on a bounded sample: the same grid and field, a few steps
+    import oracle
+    G = oracle.Grid(wl.grid.nx, wl.grid.ny, wl.grid.x_min, wl.grid.y_min, wl.grid.lx, wl.grid.ly, wl.grid.c)
+    b = wl.beam
+    B = oracle.Beam(b.mode, b.a0, b.lambda_l, b.w0, b.ramp_periods, b.longitudinal, b.ux, b.uy)
+    p = wl.packet
+    P = oracle.Packet(p.p0x, p.p0y, p.x0, p.y0, p.sigma_x, p.spin)
+    psi = oracle.init_packet(G, P)
+    tc = time.perf_counter()
+    psi = oracle.step_n(G, B, psi, 1, 0.0, wl.dt)
+    one = time.perf_counter() - tc
+    n_cpu = max(1, min(200, int(a.cpu_budget / max(one, 1e-6))))
+    tc = time.perf_counter()
+    oracle.step_n(G, B, psi, n_cpu, wl.dt, wl.dt)
+    cpu_s = time.perf_counter() - tc
+    cpu_value = cells * n_cpu / cpu_s
+    log(f"oracle: {n_cpu} steps in {cpu_s:.1f} s on {oracle.get_threads()} threads -> {cpu_value:.3e} cell-steps/s")
+
+    out = {
+        "metric": "spinor-cell steps/s at 2048^2 FP32 vs FP64 @1e-4 prob error; %HBM roofline",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * t32 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grid2048_box64_w16_a0.5 Strang steps (Dirac split-operator, FP32, "
+                               "FP64 phases and reductions)",
+                   "nx": wl.grid.nx, "ny": wl.grid.ny, "box_wavelengths": 64, "w0_wavelengths": 16,
+                   "a0": wl.beam.a0, "dt": wl.dt, "steps": a.steps},
+        "roofline": roofline,
+        "cpu_baseline": {"value": cpu_value, "unit": "cell-steps/s", "cores": oracle.get_threads(),
+                         "kind": "oracle",
+                         "sample": f"{n_cpu} FP64 steps of the same 2048x2048 workload after 1 step"},
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,10 +46,10 @@ Layout make_layout(const qw_grid& g)
     size_t o = 0;
     L.scalars = o;
     o = align_up(o + 256 * sizeof(double));
-    L.twx = o;
-    o = align_up(o + (size_t)g.nx * cs);
+    L.twx = o;  // per-pass twiddles: 2 nx entries
+    o = align_up(o + 2 * (size_t)g.nx * cs);
     L.twy = o;
-    o = align_up(o + (size_t)g.ny * cs);
+    o = align_up(o + 2 * (size_t)g.ny * cs);
     L.bx = o;
     o = align_up(o + (size_t)g.nx * cs);
     L.by = o;

@@ -71,6 +71,58 @@ __device__ __forceinline__ void bstore(cx<double> v, __amdgpu_buffer_rsrc_t r, u
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qw_v4i, v), r, voff, soff, 0);
 }
 
+// Two consecutive complex values (16 B in float, 32 B in double) at one
+// lane offset: half a cell.  The 128-bit loads and stores move whole structs
+// by bit cast (taking the vector apart element by element has been seen to
+// narrow the load to its first dword).
+template <typename T>
+struct cx2 {
+    cx<T> a, b;
+};
+__device__ __forceinline__ void bload2(cx<float>*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                       cx<float>& a, cx<float>& b)
+{
+    const cx2<float> h = __builtin_bit_cast(cx2<float>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    a = h.a;
+    b = h.b;
+}
+__device__ __forceinline__ void bload2(cx<double>*, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                       cx<double>& a, cx<double>& b)
+{
+    a = __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    b = __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0));
+}
+__device__ __forceinline__ void bstore2(cx<float> a, cx<float> b, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                        uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qw_v4i, cx2<float>{a, b}), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore2(cx<double> a, cx<double> b, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                        uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qw_v4i, a), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qw_v4i, b), r, voff + 16, soff, 0);
+}
+
+// Exchange a value with the neighbouring lane (lanes 2q <-> 2q+1) by DPP
+// quad permutation [1, 0, 3, 2].
+__device__ __forceinline__ int swap_lane_pair(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); }
+__device__ __forceinline__ float swap_lane_pair(float v)
+{
+    return __builtin_bit_cast(float, swap_lane_pair(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double swap_lane_pair(double v)
+{
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = swap_lane_pair((int)(u & 0xffffffffLL)), hi = swap_lane_pair((int)(u >> 32));
+    return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> swap_lane_pair(cx<T> v)
+{
+    return cx<T>{swap_lane_pair(v.re), swap_lane_pair(v.im)};
+}
+
 // ---------------------------------------------------------------------------
 // sin and cos of a phase given in double.  x = k pi/2 + r with pi/2 split in
 // three parts of which the first two have 33-bit mantissas (so k P1 and k P2
@@ -148,6 +200,98 @@ __device__ __forceinline__ void sincos_phase(double x, float& s, float& c)
     pc = fmaf(pc, r2, -0.5f);
     const float cr = fmaf(pc, r2, 1.0f);
     quadrant(q, sr, cr, s, c);
+}
+
+// float-only sin/cos for |x| < ~4e3: the same quadrant reduction with pi/2
+// split in three floats (12-bit first two parts, so k P1 and k P2 are exact
+// for |k| < 2^12) and the float polynomials above
+__device__ __forceinline__ void sincos_small(float x, float& s, float& c)
+{
+    const float k = rintf(x * 0.6366197466850281f);
+    float r = fmaf(-k, 1.5703125f, x);
+    r = fmaf(-k, 0.0004837512969970703f, r);
+    r = fmaf(-k, 7.549790126404332e-08f, r);
+    const int q = (int)k & 3;
+    const float r2 = r * r;
+    float ps = -2.505210838544172e-08f;
+    ps = fmaf(ps, r2, 2.7557319223985893e-06f);
+    ps = fmaf(ps, r2, -0.0001984126984126984f);
+    ps = fmaf(ps, r2, 0.008333333333333333f);
+    ps = fmaf(ps, r2, -0.16666666666666666f);
+    const float sr = fmaf(ps * r2, r, r);
+    float pc = 2.08767569878681e-09f;
+    pc = fmaf(pc, r2, -2.755731922398589e-07f);
+    pc = fmaf(pc, r2, 2.48015873015873e-05f);
+    pc = fmaf(pc, r2, -0.001388888888888889f);
+    pc = fmaf(pc, r2, 0.041666666666666664f);
+    pc = fmaf(pc, r2, -0.5f);
+    const float cr = fmaf(pc, r2, 1.0f);
+    quadrant(q, sr, cr, s, c);
+}
+__device__ __forceinline__ void sincos_small(double x, double& s, double& c) { sincos_phase(x, s, c); }
+
+// cos(th) and sin(th)/th for th^2 <= 0.01 with the series cut early:
+// float to th^4 (truncation < 2e-9), double to th^10 (< 3e-21).
+__device__ __forceinline__ void cos_sinc_short(float t2, float& C, float& Sc)
+{
+    C = fmaf(fmaf(0.041666666666666664f, t2, -0.5f), t2, 1.0f);
+    Sc = fmaf(fmaf(0.008333333333333333f, t2, -0.16666666666666666f), t2, 1.0f);
+}
+__device__ __forceinline__ void cos_sinc_short(double t2, double& C, double& Sc)
+{
+    double c = -2.755731922398589e-07;  // -1/10!
+    c = fma(c, t2, 2.48015873015873e-05);
+    c = fma(c, t2, -0.001388888888888889);
+    c = fma(c, t2, 0.041666666666666664);
+    c = fma(c, t2, -0.5);
+    C = fma(c, t2, 1.0);
+    double s = -2.505210838544172e-08;  // -1/11!
+    s = fma(s, t2, 2.7557319223985893e-06);
+    s = fma(s, t2, -0.0001984126984126984);
+    s = fma(s, t2, 0.008333333333333333);
+    s = fma(s, t2, -0.16666666666666666);
+    Sc = fma(s, t2, 1.0);
+}
+
+// cos(th) and sin(th)/th as even series in th^2 for th^2 <= 0.49 (|th| <= 0.7):
+// float keeps terms to th^10 (truncation < 3e-11), double to th^18 (< 1e-21).
+__device__ __forceinline__ void cos_sinc_series(float t2, float& C, float& Sc)
+{
+    float c = -2.755731922398589e-07f;  // -1/10!
+    c = fmaf(c, t2, 2.48015873015873e-05f);
+    c = fmaf(c, t2, -0.001388888888888889f);
+    c = fmaf(c, t2, 0.041666666666666664f);
+    c = fmaf(c, t2, -0.5f);
+    C = fmaf(c, t2, 1.0f);
+    float s = -2.505210838544172e-08f;  // -1/11!
+    s = fmaf(s, t2, 2.7557319223985893e-06f);
+    s = fmaf(s, t2, -0.0001984126984126984f);
+    s = fmaf(s, t2, 0.008333333333333333f);
+    s = fmaf(s, t2, -0.16666666666666666f);
+    Sc = fmaf(s, t2, 1.0f);
+}
+__device__ __forceinline__ void cos_sinc_series(double t2, double& C, double& Sc)
+{
+    double c = 1.5619206968586225e-16;  // 1/18!
+    c = fma(c, t2, -4.779477332387385e-14);
+    c = fma(c, t2, 1.1470745597729725e-11);
+    c = fma(c, t2, -2.08767569878681e-09);
+    c = fma(c, t2, 2.755731922398589e-07);
+    c = fma(c, t2, -2.48015873015873e-05);
+    c = fma(c, t2, 0.001388888888888889);
+    c = fma(c, t2, -0.041666666666666664);
+    c = fma(c, t2, 0.5);
+    C = fma(-c, t2, 1.0);
+    double s = 8.22063524662433e-18;  // 1/19!
+    s = fma(s, t2, -2.8114572543455206e-15);
+    s = fma(s, t2, 7.647163731819816e-13);
+    s = fma(s, t2, -1.6059043836821613e-10);
+    s = fma(s, t2, 2.505210838544172e-08);
+    s = fma(s, t2, -2.7557319223985893e-06);
+    s = fma(s, t2, 0.0001984126984126984);
+    s = fma(s, t2, -0.008333333333333333);
+    s = fma(s, t2, 0.16666666666666666);
+    Sc = fma(-s, t2, 1.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,6 +454,11 @@ struct lds_len {
     static constexpr int value = N + N / 32;
 };
 
+// Twiddles are stored per pass: for a pass (NS, R) with NS > 1 the entries
+// tw[jm R + r] = exp(-2 pi i jm r / (NS R)), jm < NS, r < R, follow the
+// previous passes' entries (sum of NS R over passes < 2N).  A butterfly reads
+// its R entries from one base: R/2 (float) or R (double) 16-byte loads with
+// immediate offsets.
 template <typename T, int N, int E, int NC, bool INV, int NS, int R>
 __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw)
 {
@@ -327,10 +476,13 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* 
         cx<T> w[R];
         if constexpr (NS > 1) {
             const int jm = j & (NS - 1);
+            const cx2<T>* tp = reinterpret_cast<const cx2<T>*>(tw + jm * R);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                cx<T> tv = tw[(jm * r) * (N / (NS * R))];
-                w[r] = INV ? conj(tv) : tv;
+            for (int r = 0; r < R; r += 2) {
+                const cx2<T> pr = tp[r / 2];
+                w[r] = pr.a;
+                w[r + 1] = INV ? conj(pr.b) : pr.b;
+                if (INV) w[r] = conj(w[r]);
             }
         }
 #pragma unroll
@@ -348,6 +500,16 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* 
         }
     }
 }
+
+// entries the per-pass twiddle table of a schedule needs
+template <int NS, int R, int... Rest>
+struct tw_len {
+    static constexpr int value = (NS > 1 ? NS * R : 0) + tw_len<NS * R, Rest...>::value;
+};
+template <int NS, int R>
+struct tw_len<NS, R> {
+    static constexpr int value = NS > 1 ? NS * R : 0;
+};
 
 // Move one component from pass-output order to the next pass's slots via LDS.
 template <typename T, int N, int E, int NS, int R>
@@ -375,7 +537,7 @@ __device__ __forceinline__ void fft_run(cx<T> (&v)[NC][E], int t, const cx<T>* _
     if constexpr (sizeof...(Rest) > 0) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) fft_exchange<T, N, E, NS, R>(v[c], t, lds);
-        fft_run<T, N, E, NC, INV, NS * R, Rest...>(v, t, tw, lds);
+        fft_run<T, N, E, NC, INV, NS * R, Rest...>(v, t, tw + (NS > 1 ? NS * R : 0), lds);
     }
 }
 
@@ -387,8 +549,9 @@ __device__ __forceinline__ void fft(sched<R...>, cx<T> (&v)[NC][E], int t, const
 
 // ---------------------------------------------------------------------------
 // 2x2 block propagator  P = C I - i (a sigma_z + bx sigma_x + by sigma_y)
-// acting on (top, bot).  Block A = (psi1, psi4) takes by as given, block
-// B = (psi2, psi3) takes -by:
+// acting on (top, bot).  In the order (psi1, psi4) block A takes the
+// coefficients as given; block B in the order (psi2, psi3) takes -by, which
+// in the order (psi3, psi2) used by the kernels becomes (C, -a, bx, by):
 //   top' = (C - i a) top + (-by - i bx) bot
 //   bot' = ( by - i bx) top + (C + i a) bot
 // Kinetic: C = cos(E dt), (a, bx, by) = sin(E dt)/E (c^2, c px, c py).

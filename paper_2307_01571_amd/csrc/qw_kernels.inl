@@ -18,8 +18,13 @@
 #include "qw_device.hpp"
 #include "qw_launch.hpp"
 
-#ifndef QW_WPE
-#define QW_WPE 2  // minimum waves per SIMD the register allocation must allow
+// minimum waves per SIMD the register allocation must allow (measured best
+// on MI355X at 2048^2: 3 for the row passes, 4 for the column passes)
+#ifndef QW_WPE_ROW
+#define QW_WPE_ROW 3
+#endif
+#ifndef QW_WPE_COL
+#define QW_WPE_COL 4
 #endif
 
 namespace qw {
@@ -62,9 +67,19 @@ QW_PLAN(double, 2048, 8, 8, 8, 8, 4)
 QW_PLAN(double, 4096, 8, 8, 8, 8, 8)
 #undef QW_PLAN
 
-// Lanes come in pairs: lane 2q + 0 holds spin block A = (psi1, psi4) and
-// lane 2q + 1 block B = (psi2, psi3) of the same cells, so a line of length N
-// takes L = 2 N/E lanes and each lane keeps 2 E complex values in registers.
+// Lanes come in pairs over the same cells: lane 2q + 0 holds spin block A as
+// (top, bot) = (psi1, psi4), lane 2q + 1 block B as (top, bot) = (psi3, psi2).
+// Each lane loads one contiguous half cell -- (psi1, psi2) or (psi3, psi4) --
+// and the pair swaps its second values, so every load and store instruction
+// of a wave covers contiguous memory.  A line of length N takes L = 2 N/E
+// lanes and each lane keeps 2 E complex values in registers.
+template <typename T, int N, typename S = typename plan<T, N>::S>
+struct tw_len_of;
+template <typename T, int N, int... R>
+struct tw_len_of<T, N, sched<R...>> {
+    static constexpr int value = tw_len<1, R...>::value;
+};
+
 template <typename T, int N>
 struct shape {
     static constexpr int E = plan<T, N>::E;
@@ -72,7 +87,7 @@ struct shape {
     static constexpr int L = 2 * NT;                                  // lanes per line
     static constexpr int RPW = L >= 256 ? 1 : 256 / L;                // rows per workgroup
     static constexpr int TX = L >= 512 ? 1 : (L >= 128 ? 2 : 256 / L);  // columns per workgroup
-    static constexpr int LL = lds_len<N>::value;
+    static constexpr int LL = lds_len<N>::value + 1;  // +1 shifts the two blocks' buffers by two banks
 };
 
 // ---------------------------------------------------------------------------
@@ -91,41 +106,69 @@ __device__ __forceinline__ double field_time_factor(int mode, double t, double o
     return f * c;
 }
 
-// cos(th) and sin(th)/|A| = (c tau) sin(th)/th for th = c |A| tau; the series
-// below the threshold also covers |A| = 0 exactly.
-__device__ __forceinline__ void cos_sinc(float th, float ctau, float amag, float& C, float& S)
+// Interaction propagator coefficients for A = (ax, ay) acting for tau:
+// C = cos(th), S = sin(th)/|A| = (c tau) sin(th)/th with th = c |A| tau.
+// SERIES 2 (th^2 <= 0.01) and 1 (th^2 <= 0.49, which covers every field of
+// interest at these time steps): the even series in th^2, short or long,
+// with no sqrt and no division, exact at |A| = 0.  SERIES 0: the reduced
+// sin/cos and one division.  The choice is made once per row from a bound
+// on |A|, so each variant is straight-line.
+template <int SERIES, typename T>
+__device__ __forceinline__ void interaction_coeffs(T ax, T ay, T ctau, T& C, T& S)
 {
-    if (fabsf(th) < 1e-2f) {
-        float t2 = th * th;
-        C = 1.0f - t2 * (0.5f - t2 * (1.0f / 24.0f));
-        S = ctau * (1.0f - t2 * (1.0f / 6.0f - t2 * (1.0f / 120.0f)));
+    const T a2 = ax * ax + ay * ay;
+    if constexpr (SERIES == 2) {
+        T sc;
+        cos_sinc_short(ctau * ctau * a2, C, sc);
+        S = ctau * sc;
+    } else if constexpr (SERIES == 1) {
+        T sc;
+        cos_sinc_series(ctau * ctau * a2, C, sc);
+        S = ctau * sc;
     } else {
-        float sn, cs;
-        sincos_phase((double)th, sn, cs);
-        C = cs;
-        S = sn / amag;
-    }
-}
-__device__ __forceinline__ void cos_sinc(double th, double ctau, double amag, double& C, double& S)
-{
-    if (fabs(th) < 1e-4) {
-        double t2 = th * th;
-        C = 1.0 - t2 * (0.5 - t2 * (1.0 / 24.0));
-        S = ctau * (1.0 - t2 * (1.0 / 6.0 - t2 * (1.0 / 120.0)));
-    } else {
-        double sn, cs;
-        sincos_phase(th, sn, cs);
-        C = cs;
-        S = sn / amag;
+        const T amag = sqrt(a2);
+        T sn;
+        sincos_small(ctau * amag, sn, C);
+        S = amag > (T)0 ? sn / amag : ctau;
     }
 }
 
-// the kinetic phase E dt is formed in double and reduced in double; the
-// float form evaluates sin/cos of the reduced argument in float
-template <typename T>
-__device__ __forceinline__ void phase_sincos(double ph, T& s, T& c)
+template <int SERIES, typename T, int E, int NT>
+__device__ __forceinline__ void apply_interaction(cx<T> (&v)[2][E], const cx<T>* bxt, int t, T ax_row, T ay_row,
+                                                  T ctau)
 {
-    sincos_phase(ph, s, c);
+    asm volatile("" ::: "memory");  // table loads stay here, not in the transform above
+    int tt = t;
+    asm volatile("" : "+v"(tt));
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const cx<T> xb = bxt[tt + NT * m];
+        const T ax = ax_row * xb.im, ay = ay_row * xb.re;
+        T C, Sn;
+        interaction_coeffs<SERIES>(ax, ay, ctau, C, Sn);
+        block_prop(v[0][m], v[1][m], C, (T)0, Sn * ax, Sn * ay);
+    }
+}
+
+// Kinetic phase phi = sqrt(X) (X = phi^2 >= (c^2 dt)^2 > 0) with sin, cos and
+// 1/phi.  Double: library sqrt and a division.  Float: phi to ~1e-15 relative
+// from the float reciprocal square root and one Newton step in double, then
+// the quadrant reduction in double and the float polynomials; 1/phi is the
+// float reciprocal square root itself.
+__device__ __forceinline__ void kinetic_phase(double X, double& s, double& c, double& inv_phi)
+{
+    const double phi = sqrt(X);
+    sincos_phase(phi, s, c);
+    inv_phi = 1.0 / phi;
+}
+__device__ __forceinline__ void kinetic_phase(double X, float& s, float& c, float& inv_phi)
+{
+    const float r = __builtin_amdgcn_rsqf((float)X);
+    const double rd = (double)r;
+    const double y0 = X * rd;
+    const double phi = fma(0.5 * rd, fma(-y0, y0, X), y0);
+    sincos_phase(phi, s, c);
+    inv_phi = r;
 }
 
 __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k : k - n; }
@@ -134,7 +177,7 @@ __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k :
 // row pass
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE))) void row_pass(RowArgs a)
+__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_ROW))) void row_pass(RowArgs a)
 {
     using S = shape<T, N>;
     constexpr int E = S::E, NT = S::NT, L = S::L, RPW = S::RPW, LL = S::LL;
@@ -151,16 +194,16 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
     // non-live row is pointed past the array (reads zero, writes dropped)
     constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
     const uint32_t bytes = (uint32_t)a.ny * N * CB;
-    const uint32_t lane = live ? ((uint32_t)y * N + t) * CB : bytes;
-    const uint32_t o0 = lane + (blk ? 1u : 0u) * sizeof(cx<T>), o1 = lane + (blk ? 2u : 3u) * sizeof(cx<T>);
+    const uint32_t lane = live ? ((uint32_t)y * N + t) * CB + blk * (CB / 2) : bytes;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, bytes);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, bytes);
 
     cx<T> v[2][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        v[0][m] = bload((cx<T>*)nullptr, rs, o0, m * NT * CB);
-        v[1][m] = bload((cx<T>*)nullptr, rs, o1, m * NT * CB);
+        cx<T> f;
+        bload2((cx<T>*)nullptr, rs, lane, m * NT * CB, v[0][m], f);
+        v[1][m] = swap_lane_pair(f);
     }
 
     if constexpr (MODE == ROW_FWD_NORM) {
@@ -187,27 +230,18 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
         fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
 
     if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_LAST) {
-        // interaction propagator V(t, tau) with A evaluated from the field tables
+        // interaction propagator V(t, tau) with A evaluated from the field tables;
+        // |A|^2 <= s(t)^2 (Y0^2 + Y1^2) on this row bounds the angle
         const double tk = a.t0 + (double)a.k * a.dt;
         const T sfac = (T)field_time_factor(a.beam_mode, tk, a.omega, a.t_ramp, a.ramp_k);
-        const T tau = (T)(a.tau_frac * a.dt);
-        const T c = (T)a.c;
+        const T ctau = (T)(a.c * a.tau_frac * a.dt);
         const cx<T>* bxt = reinterpret_cast<const cx<T>*>(a.beam_x);
         const cx<T> yb = reinterpret_cast<const cx<T>*>(a.beam_y)[live ? y : 0];
         const T ay_row = sfac * yb.re, ax_row = sfac * yb.im;
-        const T sgn = blk ? (T)-1 : (T)1;
-        asm volatile("" ::: "memory");  // table loads stay here, not in the transform above
-        int tt = t;
-        asm volatile("" : "+v"(tt));
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const cx<T> xb = bxt[tt + NT * m];
-            const T ax = ax_row * xb.im, ay = ay_row * xb.re;
-            const T amag = sqrt(ax * ax + ay * ay);
-            T C, Sn;
-            cos_sinc(c * amag * tau, c * tau, amag, C, Sn);
-            block_prop(v[0][m], v[1][m], C, (T)0, Sn * ax, sgn * Sn * ay);
-        }
+        const T bound = ctau * ctau * (ay_row * ay_row + ax_row * ax_row);
+        if (bound <= (T)0.01) apply_interaction<2, T, E, NT>(v, bxt, t, ax_row, ay_row, ctau);
+        else if (bound <= (T)0.49) apply_interaction<1, T, E, NT>(v, bxt, t, ax_row, ay_row, ctau);
+        else apply_interaction<0, T, E, NT>(v, bxt, t, ax_row, ay_row, ctau);
     }
 
     if constexpr (MODE == ROW_INV_SCALE) {
@@ -223,17 +257,14 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
         fft<T, N, E, 2, false>(typename plan<T, N>::S{}, v, t, tw, lb);
 
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        bstore(v[0][m], rd, o0, m * NT * CB);
-        bstore(v[1][m], rd, o1, m * NT * CB);
-    }
+    for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rd, lane, m * NT * CB);
 }
 
 // ---------------------------------------------------------------------------
 // column pass
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE))) void col_pass(ColArgs a)
+__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_COL))) void col_pass(ColArgs a)
 {
     using S = shape<T, N>;
     constexpr int E = S::E, NT = S::NT, TX = S::TX, LL = S::LL;
@@ -243,22 +274,26 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     const int blk = threadIdx.x & 1;
     const int cl = (threadIdx.x >> 1) % TX;
     const int t = (threadIdx.x >> 1) / TX;
-    const int x = blockIdx.x * TX + cl;
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+    // give each XCD a contiguous run of tiles -- neighbouring tiles share
+    // cache lines and then meet in the same L2
+    const int tile = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const int x = tile * TX + cl;
     const bool live = x < a.nx;
     cx<T>* lb = lds + (2 * cl + blk) * LL;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twy);
     constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
     const uint32_t bytes = (uint32_t)a.nx * N * CB;
-    const uint32_t lane = live ? ((uint32_t)t * a.nx + x) * CB : bytes;
-    const uint32_t o0 = lane + (blk ? 1u : 0u) * sizeof(cx<T>), o1 = lane + (blk ? 2u : 3u) * sizeof(cx<T>);
+    const uint32_t lane = live ? ((uint32_t)t * a.nx + x) * CB + blk * (CB / 2) : bytes;
     const uint32_t mstride = (uint32_t)NT * a.nx * CB;  // bytes between a lane's elements
     const __amdgpu_buffer_rsrc_t rp = make_rsrc(a.psi, bytes);
 
     cx<T> v[2][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-        v[0][m] = bload((cx<T>*)nullptr, rp, o0, m * mstride);
-        v[1][m] = bload((cx<T>*)nullptr, rp, o1, m * mstride);
+        cx<T> f;
+        bload2((cx<T>*)nullptr, rp, lane, m * mstride, v[0][m], f);
+        v[1][m] = swap_lane_pair(f);
     }
 
     if constexpr (MODE == COL_INV) {
@@ -272,37 +307,48 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     const double px = a.dkx * (double)kxs;
 
     if constexpr (MODE == COL_PROP) {
-        // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny)
+        // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny).
+        // With phi = E dt: phi^2 = X0 + (c dt py)^2, X0 = (c dt)^2 (c^2 + px^2) per lane,
+        // and (a, bx, by) = sin(phi)/phi (c^2, c px, c py) dt.
+        const double cdt = c * a.dt;
+        const double X0 = cdt * cdt * (c * c + px * px);
+        const double cdtdky = cdt * a.dky;
         const T nrm = (T)a.inv_cells;
-        const T cT = (T)c;
-        const T sgn = blk ? (T)-1 : (T)1;
+        const T sgn = blk ? (T)-1 : (T)1;  // sign of the sigma_z term in each lane's order
+        const T ka = sgn * (T)(c * cdt * a.inv_cells);      // c^2 dt / (nx ny)
+        const T kx = (T)(cdt * px * a.inv_cells);           // c px dt / (nx ny)
+        const T ky = (T)(cdt * a.dky * a.inv_cells);        // c dky dt / (nx ny)
+        if (a.dt != 0.0) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int kys = signed_idx(t + NT * m, N);
-            const double py = a.dky * (double)kys;
-            const double en = c * sqrt(c * c + px * px + py * py);
-            T sn, cs;
-            phase_sincos(en * a.dt, sn, cs);
-            const T se = sn / (T)en * nrm;  // sin(E dt)/(E nx ny)
-            block_prop(v[0][m], v[1][m], cs * nrm, se * cT * cT, se * cT * (T)px, sgn * se * cT * (T)py);
+            for (int m = 0; m < E; ++m) {
+                const int kys = signed_idx(t + NT * m, N);
+                const double u = cdtdky * (double)kys;
+                T sn, cs, inv_phi;
+                kinetic_phase(fma(u, u, X0), sn, cs, inv_phi);
+                const T q = sn * inv_phi;  // sin(phi)/phi
+                block_prop(v[0][m], v[1][m], cs * nrm, q * ka, q * kx, q * ky * (T)kys);
+            }
+        } else {  // K(p, 0) = I: only the transform normalisation (phi = 0 has no 1/phi)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                v[0][m] = scale(v[0][m], nrm);
+                v[1][m] = scale(v[1][m], nrm);
+            }
         }
         fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
     }
 
     if constexpr (MODE == COL_PROP || MODE == COL_INV) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) {
-            bstore(v[0][m], rp, o0, m * mstride);
-            bstore(v[1][m], rp, o1, m * mstride);
-        }
+        for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rp, lane, m * mstride);
     }
 
     if constexpr (MODE == COL_OBS) {
         // spin projections onto the unit bispinors u^+-(p) (Eq. 9, 18):
         //   c^s = sqrt((E + c^2)/(2E)) (aA + s aB)/sqrt2,
         //   aA = phi1 + k (px - i py) phi4,  aB = phi2 + k (px + i py) phi3,  k = c/(E + c^2)
-        // Block A lanes hold (phi1, phi4), block B lanes (phi2, phi3); the
-        // partner lane's value comes by a lane shuffle.
+        // Block A lanes hold (phi1, phi4), block B lanes (phi3, phi2); each
+        // forms its own aA or aB and takes the partner's by a lane shuffle.
         double sw = 0.0, sp = 0.0, sm = 0.0;
         const double sg = blk ? -1.0 : 1.0;
 #pragma unroll
@@ -312,8 +358,9 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
             const double en = c * sqrt(c * c + px * px + py * py);
             const double kk = c / (en + c * c);
             const double tr = v[0][m].re, ti = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
-            // top + k (px - i sg py) bot
-            const double ar = tr + kk * (px * br + sg * py * bi), ai = ti + kk * (px * bi - sg * py * br);
+            // u = phi1 or phi2, w = phi4 or phi3:  u + k (px - i sg py) w
+            const double ur = blk ? br : tr, ui = blk ? bi : ti, wr = blk ? tr : br, wi = blk ? ti : bi;
+            const double ar = ur + kk * (px * wr + sg * py * wi), ai = ui + kk * (px * wi - sg * py * wr);
             const double or_ = __shfl_xor(ar, 1), oi = __shfl_xor(ai, 1);
             if (live) {
                 sw += tr * tr + ti * ti + br * br + bi * bi;
@@ -342,10 +389,10 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
         }
         if (threadIdx.x == 0) {
             const int nb = 2 * a.n_max + 1;
-            double* out = a.partial + (size_t)blockIdx.x * a.partial_stride;
+            double* out = a.partial + (size_t)tile * a.partial_stride;
             for (int i = 0; i < 3 * nb + 3; ++i) out[i] = 0.0;
             for (int qc = 0; qc < TX; ++qc) {
-                const int xq = blockIdx.x * TX + qc;
+                const int xq = tile * TX + qc;
                 if (xq >= a.nx) break;
                 const double w = red[2 * qc] + red[2 * qc + 1];
                 const double wp = red[nthr + 2 * qc], wm = red[2 * nthr + 2 * qc];
@@ -372,15 +419,34 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
 // ---------------------------------------------------------------------------
 // tables
 // ---------------------------------------------------------------------------
-// twiddles exp(-2 pi i k / n), k < n, evaluated in double
-template <typename T>
-__global__ void twiddle_table(cx<T>* tw, int n)
+// per-pass twiddles of the plan for length N (layout in fft_pass), in double
+template <int NS, int R, int... Rest>
+__device__ void fill_pass_twiddles(cx<double>* tmp, int i, int off)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double s, c;
-    sincospi(2.0 * (double)k / (double)n, &s, &c);
-    tw[k] = cx<T>{(T)c, (T)-s};
+    if constexpr (NS > 1) {
+        if (i >= off && i < off + NS * R) {
+            const int jm = (i - off) / R, r = (i - off) % R;
+            double s, c;
+            sincospi(2.0 * (double)(jm * r) / (double)(NS * R), &s, &c);
+            tmp[0] = cx<double>{c, -s};
+        }
+    }
+    if constexpr (sizeof...(Rest) > 0) fill_pass_twiddles<NS * R, Rest...>(tmp, i, off + (NS > 1 ? NS * R : 0));
+}
+
+template <typename T, int... R>
+__device__ void pass_twiddle(sched<R...>, cx<T>* tw, int i)
+{
+    cx<double> v{1.0, 0.0};
+    fill_pass_twiddles<1, R...>(&v, i, 0);
+    tw[i] = cx<T>{(T)v.re, (T)v.im};
+}
+
+template <typename T, int N>
+__global__ void twiddle_table(cx<T>* tw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * N) pass_twiddle<T>(typename plan<T, N>::S{}, tw, i);
 }
 
 // field tables: beam_x[i] = (X0, X1) and beam_y[j] = (Y0, Y1) with
@@ -532,14 +598,27 @@ int col_blocks(int nx, int ny)
 #undef QW_CALL
     return -1;
 }
-#undef QW_SIZE_SWITCH
 
+template <typename T, int N>
+hipError_t twiddles_n(void* tw, hipStream_t st)
+{
+    static_assert(tw_len_of<T, N>::value <= 2 * N, "twiddle table larger than its slot");
+    hipLaunchKernelGGL((twiddle_table<T, N>), dim3((2 * N + 255) / 256), dim3(256), 0, st,
+                       reinterpret_cast<cx<T>*>(tw));
+    return hipGetLastError();
+}
+
+// per-pass twiddles for length n into 2n entries at tw
 template <typename T>
 hipError_t launch_twiddles(void* tw, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL(twiddle_table<T>, dim3((n + 255) / 256), dim3(256), 0, st, reinterpret_cast<cx<T>*>(tw), n);
-    return hipGetLastError();
+#define QW_CALL(NN) twiddles_n<T, NN>(tw, st)
+    QW_SIZE_SWITCH(n, QW_CALL)
+#undef QW_CALL
+    return hipErrorInvalidValue;
 }
+
+#undef QW_SIZE_SWITCH
 
 template <typename T>
 hipError_t launch_beam_tables(void* bx, void* by, const BeamArgs& b, hipStream_t st)

@@ -18,7 +18,7 @@ constexpr int QW_BEAM_UNIFORM_ = 2;
 struct RowArgs {
     const void* src;          // [ny][nx][4] complex T
     void* dst;                // may equal src (in place)
-    const void* twx;          // nx twiddles exp(-2 pi i k / nx)
+    const void* twx;          // per-pass twiddles of the x transform (2 nx entries)
     const void* beam_x;       // nx field factors (X0, X1)
     const void* beam_y;       // ny field factors (Y0, Y1)
     double* rownorm;          // ROW_FWD_NORM: ny row sums of |psi|^2
@@ -33,7 +33,7 @@ struct RowArgs {
 
 struct ColArgs {
     void* psi;
-    const void* twy;  // ny twiddles
+    const void* twy;  // per-pass twiddles of the y transform (2 ny entries)
     int nx;
     double dkx, dky, c, dt, inv_cells;
     double* partial;  // COL_OBS: per-workgroup sums, partial_stride doubles each
