@@ -27,6 +27,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_CELL_PASS = {"f32": 64, "f64": 128}  # read + write of 4 complex per pass
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_2048sq_f32.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP library sources; measured traffic is reported only for the sources it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2307_01571_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".inl", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if still current."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
 def log(*a):
@@ -120,9 +146,13 @@ def main():
         per[k] = {"launches": int(cnt), "avg_us": avg_s * 1e6, "GBps": gbs}
         log(f"  {k} pass: {cnt:.0f} launches, avg {avg_s * 1e6:.2f} us, {gbs:.0f} GB/s algorithmic")
     dom = max(per, key=lambda k: per[k]["avg_us"])
-    roofline = {"bound": "hbm", "kernel": "col_pass" if dom == "col" else "row_pass",
+    dom_name = "col_pass" if dom == "col" else "row_pass"
+    traffic = measured_traffic(dom_name)
+    roofline = {"bound": "hbm", "kernel": dom_name,
                 "achieved": round(per[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(per[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(per[dom]["GBps"] / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / (per[dom]["avg_us"] * 1e-6) / 1e9, 1),
+                "traffic_bytes_per_launch": traffic,
                 "bytes_per_launch": BYTES_PER_CELL_PASS["f32"] * cells,
                 "avg_launch_us": {k: round(v["avg_us"], 3) for k, v in per.items()},
                 "step_GBps": round(2 * BYTES_PER_CELL_PASS["f32"] * cells * a.steps / t32 / 1e9, 1)}

@@ -2,7 +2,7 @@
 // validation, workspace carving, table set-up and the launch sequence of the
 // split-operator step.  No device memory is allocated here; every launch goes
 // to the caller's stream.
-#include "../../include/qw.h"
+#include "qw.h"
 
 #include <hip/hip_runtime.h>
 
@@ -32,6 +32,7 @@ struct Layout {
     size_t scalars;   // 256 doubles: [0] packet norm, [8..) observables results
     size_t twx, twy;  // twiddle tables
     size_t bx, by;    // field tables
+    size_t ktab;      // kinetic table, (nx/2+1)(ny/2+1) complex
     size_t rownorm;   // ny doubles
     size_t partial;   // column-pass workgroups x kPartialStride doubles
     size_t plane;     // one state-sized array
@@ -54,6 +55,8 @@ Layout make_layout(const qw_grid& g)
     o = align_up(o + (size_t)g.nx * cs);
     L.by = o;
     o = align_up(o + (size_t)g.ny * cs);
+    L.ktab = o;
+    o = align_up(o + (size_t)(g.nx / 2 + 1) * (g.ny / 2 + 1) * cs);
     L.rownorm = o;
     o = align_up(o + (size_t)g.ny * sizeof(double));
     L.partial = o;
@@ -76,6 +79,8 @@ struct qw_ctx_s {
     qw_beam b{};
     bool beam_set = false;
     bool tables_dirty = true;
+    bool ktab_valid = false;
+    double ktab_dt = 0.0;  // time step the kinetic table was built for
     char* ws = nullptr;
     size_t ws_bytes = 0;
     Layout lay{};
@@ -196,6 +201,26 @@ int ensure_tables(qw_ctx h, hipStream_t s)
     return QW_OK;
 }
 
+// the kinetic table depends on dt only (and the grid): rebuild when dt changes
+int ensure_kinetic_table(qw_ctx h, double dt, hipStream_t s)
+{
+    if (h->ktab_valid && h->ktab_dt == dt) return QW_OK;
+    qw::KineticArgs k{};
+    k.nx = h->g.nx;
+    k.ny = h->g.ny;
+    k.dkx = 2.0 * kPi / h->g.lx;
+    k.dky = 2.0 * kPi / h->g.ly;
+    k.c = h->g.c;
+    k.dt = dt;
+    k.inv_cells = 1.0 / ((double)h->g.nx * (double)h->g.ny);
+    void* kt = h->ws + h->lay.ktab;
+    hipError_t e = f32(h) ? qw::launch_kinetic_table_f32(kt, k, s) : qw::launch_kinetic_table_f64(kt, k, s);
+    if (e != hipSuccess) return hip_fail(h, e, "kinetic table kernel");
+    h->ktab_valid = true;
+    h->ktab_dt = dt;
+    return QW_OK;
+}
+
 qw::RowArgs row_args(qw_ctx h, const void* src, void* dst)
 {
     qw::RowArgs a{};
@@ -223,6 +248,7 @@ qw::ColArgs col_args(qw_ctx h, void* psi)
     qw::ColArgs a{};
     a.psi = psi;
     a.twy = h->ws + h->lay.twy;
+    a.ktab = h->ws + h->lay.ktab;
     a.nx = h->g.nx;
     a.dkx = 2.0 * kPi / h->g.lx;
     a.dky = 2.0 * kPi / h->g.ly;
@@ -358,8 +384,15 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
         const double tmax = std::fmax(std::fabs(t0), std::fabs(t0 + (double)n * dt));
         if (om * tmax > 1.6e6) return fail(h, QW_E_ARG, "|omega t| = %g exceeds 1.6e6", om * tmax);
     }
+    // |E dt| must stay inside the exact range of the in-kernel phase reduction
+    {
+        const double px = 0.5 * h->g.nx * 2.0 * kPi / h->g.lx, py = 0.5 * h->g.ny * 2.0 * kPi / h->g.ly;
+        const double emax = h->g.c * std::sqrt(h->g.c * h->g.c + px * px + py * py);
+        if (emax * std::fabs(dt) > 1.6e6) return fail(h, QW_E_ARG, "|E dt| = %g exceeds 1.6e6", emax * std::fabs(dt));
+    }
     hipStream_t s = as_stream(hip_stream);
     int rc = ensure_tables(h, s);
+    if (rc == QW_OK) rc = ensure_kinetic_table(h, dt, s);
     if (rc != QW_OK) return rc;
     qw::RowArgs r = row_args(h, psi, psi);
     r.t0 = t0;

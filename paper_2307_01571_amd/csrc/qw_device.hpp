@@ -447,11 +447,15 @@ __device__ __forceinline__ void dft(cx<T>* x)
 template <int... R>
 struct sched {};
 
-// LDS padding: one extra element every 32 breaks the power-of-two strides
-__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> 5); }
+// LDS padding: one extra element every 2^QW_LDS_PADSH breaks the
+// power-of-two strides of the exchanges
+#ifndef QW_LDS_PADSH
+#define QW_LDS_PADSH 5
+#endif
+__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> QW_LDS_PADSH); }
 template <int N>
 struct lds_len {
-    static constexpr int value = N + N / 32;
+    static constexpr int value = N + (N >> QW_LDS_PADSH);
 };
 
 // Twiddles are stored per pass: for a pass (NS, R) with NS > 1 the entries
@@ -459,32 +463,37 @@ struct lds_len {
 // previous passes' entries (sum of NS R over passes < 2N).  A butterfly reads
 // its R entries from one base: R/2 (float) or R (double) 16-byte loads with
 // immediate offsets.
-template <typename T, int N, int E, int NC, bool INV, int NS, int R>
-__device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw)
+template <typename T, int N, int E, bool INV, int NS, int R>
+__device__ __forceinline__ void load_twiddles(cx<T> (&w)[E / R][R], int t, const cx<T>* __restrict__ tw)
 {
     constexpr int NT = N / E;
-    constexpr int B = E / R;
-    static_assert(E % R == 0, "radix must divide the per-thread element count");
-    // keep this pass's twiddle loads and their offsets inside the pass:
-    // hoisting or sharing them across passes would hold them all in registers
-    asm volatile("" ::: "memory");
-    int tt = t;
-    asm volatile("" : "+v"(tt));
+    if constexpr (NS > 1) {
+        // keep these loads and their offsets here: hoisting or sharing them
+        // across passes would hold every pass's twiddles in registers
+        asm volatile("" ::: "memory");
+        int tt = t;
+        asm volatile("" : "+v"(tt));
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const int j = tt + NT * b;
-        cx<T> w[R];
-        if constexpr (NS > 1) {
-            const int jm = j & (NS - 1);
+        for (int b = 0; b < E / R; ++b) {
+            const int jm = (tt + NT * b) & (NS - 1);
             const cx2<T>* tp = reinterpret_cast<const cx2<T>*>(tw + jm * R);
 #pragma unroll
             for (int r = 0; r < R; r += 2) {
                 const cx2<T> pr = tp[r / 2];
-                w[r] = pr.a;
-                w[r + 1] = INV ? conj(pr.b) : pr.b;
-                if (INV) w[r] = conj(w[r]);
+                w[b][r] = INV ? conj(pr.a) : pr.a;
+                w[b][r + 1] = INV ? conj(pr.b) : pr.b;
             }
         }
+    }
+}
+
+template <typename T, int N, int E, int NC, bool INV, int NS, int R>
+__device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], const cx<T> (&w)[E / R][R])
+{
+    constexpr int B = E / R;
+    static_assert(E % R == 0, "radix must divide the per-thread element count");
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             cx<T> x[R];
@@ -492,7 +501,7 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* 
             for (int r = 0; r < R; ++r) x[r] = v[c][b + r * B];
             if constexpr (NS > 1) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) x[r] = mul(x[r], w[r]);
+                for (int r = 1; r < R; ++r) x[r] = mul(x[r], w[b][r]);
             }
             dft<T, R, INV>(x);
 #pragma unroll
@@ -500,6 +509,11 @@ __device__ __forceinline__ void fft_pass(cx<T> (&v)[NC][E], int t, const cx<T>* 
         }
     }
 }
+
+template <int R, int... Rest>
+struct first_of {
+    static constexpr int value = R;
+};
 
 // entries the per-pass twiddle table of a schedule needs
 template <int NS, int R, int... Rest>
@@ -530,21 +544,34 @@ __device__ __forceinline__ void fft_exchange(cx<T> (&vc)[E], int t, cx<T>* lds)
     __syncthreads();
 }
 
+// Runs the passes.  The twiddles of pass p+1 are loaded before pass p's LDS
+// exchange (QW_TW_PREFETCH), so their latency hides behind it.
+#ifndef QW_TW_PREFETCH
+#define QW_TW_PREFETCH 1
+#endif
 template <typename T, int N, int E, int NC, bool INV, int NS, int R, int... Rest>
-__device__ __forceinline__ void fft_run(cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw, cx<T>* lds)
+__device__ __forceinline__ void fft_run(cx<T> (&v)[NC][E], const cx<T> (&w)[E / R][R], int t,
+                                        const cx<T>* __restrict__ tw, cx<T>* lds)
 {
-    fft_pass<T, N, E, NC, INV, NS, R>(v, t, tw);
+    fft_pass<T, N, E, NC, INV, NS, R>(v, w);
     if constexpr (sizeof...(Rest) > 0) {
+        constexpr int R2 = first_of<Rest...>::value;
+        const cx<T>* tw2 = tw + (NS > 1 ? NS * R : 0);
+        cx<T> w2[E / R2][R2];
+        if constexpr (QW_TW_PREFETCH) load_twiddles<T, N, E, INV, NS * R, R2>(w2, t, tw2);
 #pragma unroll
         for (int c = 0; c < NC; ++c) fft_exchange<T, N, E, NS, R>(v[c], t, lds);
-        fft_run<T, N, E, NC, INV, NS * R, Rest...>(v, t, tw + (NS > 1 ? NS * R : 0), lds);
+        if constexpr (!QW_TW_PREFETCH) load_twiddles<T, N, E, INV, NS * R, R2>(w2, t, tw2);
+        fft_run<T, N, E, NC, INV, NS * R, Rest...>(v, w2, t, tw2, lds);
     }
 }
 
-template <typename T, int N, int E, int NC, bool INV, int... R>
-__device__ __forceinline__ void fft(sched<R...>, cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw, cx<T>* lds)
+template <typename T, int N, int E, int NC, bool INV, int R0, int... R>
+__device__ __forceinline__ void fft(sched<R0, R...>, cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw,
+                                    cx<T>* lds)
 {
-    fft_run<T, N, E, NC, INV, 1, R...>(v, t, tw, lds);
+    cx<T> w0[E / R0][R0];  // the first pass (stride 1) has no twiddles
+    fft_run<T, N, E, NC, INV, 1, R0, R...>(v, w0, t, tw, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,10 +18,22 @@
 #include "qw_device.hpp"
 #include "qw_launch.hpp"
 
-// minimum waves per SIMD the register allocation must allow (measured best
-// on MI355X at 2048^2: 3 for the row passes, 4 for the column passes)
+// Tuning constants (measured best on MI355X at 2048^2):
+//  - per-lane-group LDS buffer padding in elements (row / column passes);
+//  - columns per workgroup once a column needs >= 128 lanes;
+//  - minimum waves per SIMD the register allocation must allow: 2 for the
+//    row passes, 4 for the column passes with two columns per workgroup.
+#ifndef QW_LDS_EXTRA_ROW
+#define QW_LDS_EXTRA_ROW 8
+#endif
+#ifndef QW_LDS_EXTRA_COL
+#define QW_LDS_EXTRA_COL 4
+#endif
+#ifndef QW_TX_COL
+#define QW_TX_COL 2
+#endif
 #ifndef QW_WPE_ROW
-#define QW_WPE_ROW 3
+#define QW_WPE_ROW 2
 #endif
 #ifndef QW_WPE_COL
 #define QW_WPE_COL 4
@@ -86,8 +98,11 @@ struct shape {
     static constexpr int NT = N / E;                                  // lanes per line and block
     static constexpr int L = 2 * NT;                                  // lanes per line
     static constexpr int RPW = L >= 256 ? 1 : 256 / L;                // rows per workgroup
-    static constexpr int TX = L >= 512 ? 1 : (L >= 128 ? 2 : 256 / L);  // columns per workgroup
-    static constexpr int LL = lds_len<N>::value + 1;  // +1 shifts the two blocks' buffers by two banks
+    static constexpr int TX = L >= 512 ? 1 : (L >= 128 ? QW_TX_COL : 256 / L);  // columns per workgroup
+    // per-lane-group LDS buffer strides (elements); the extra elements move
+    // the groups' buffers onto different banks
+    static constexpr int LLR = lds_len<N>::value + QW_LDS_EXTRA_ROW;
+    static constexpr int LLC = lds_len<N>::value + QW_LDS_EXTRA_COL;
 };
 
 // ---------------------------------------------------------------------------
@@ -150,27 +165,6 @@ __device__ __forceinline__ void apply_interaction(cx<T> (&v)[2][E], const cx<T>*
     }
 }
 
-// Kinetic phase phi = sqrt(X) (X = phi^2 >= (c^2 dt)^2 > 0) with sin, cos and
-// 1/phi.  Double: library sqrt and a division.  Float: phi to ~1e-15 relative
-// from the float reciprocal square root and one Newton step in double, then
-// the quadrant reduction in double and the float polynomials; 1/phi is the
-// float reciprocal square root itself.
-__device__ __forceinline__ void kinetic_phase(double X, double& s, double& c, double& inv_phi)
-{
-    const double phi = sqrt(X);
-    sincos_phase(phi, s, c);
-    inv_phi = 1.0 / phi;
-}
-__device__ __forceinline__ void kinetic_phase(double X, float& s, float& c, float& inv_phi)
-{
-    const float r = __builtin_amdgcn_rsqf((float)X);
-    const double rd = (double)r;
-    const double y0 = X * rd;
-    const double phi = fma(0.5 * rd, fma(-y0, y0, X), y0);
-    sincos_phase(phi, s, c);
-    inv_phi = r;
-}
-
 __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k : k - n; }
 
 // ---------------------------------------------------------------------------
@@ -180,7 +174,7 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_ROW))) void row_pass(RowArgs a)
 {
     using S = shape<T, N>;
-    constexpr int E = S::E, NT = S::NT, L = S::L, RPW = S::RPW, LL = S::LL;
+    constexpr int E = S::E, NT = S::NT, L = S::L, RPW = S::RPW, LL = S::LLR;
     __shared__ cx<T> lds[RPW * 2 * LL];
     const int blk = threadIdx.x & 1;  // 0: (psi1, psi4), 1: (psi2, psi3)
     const int q = threadIdx.x >> 1;
@@ -267,7 +261,7 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_COL))) void col_pass(ColArgs a)
 {
     using S = shape<T, N>;
-    constexpr int E = S::E, NT = S::NT, TX = S::TX, LL = S::LL;
+    constexpr int E = S::E, NT = S::NT, TX = S::TX, LL = S::LLC;
     __shared__ cx<T> lds[TX * 2 * LL];
     // lane order: block fastest, then the column within the tile, then t, so
     // a wave reads TX whole cells of each of several rows
@@ -307,33 +301,23 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     const double px = a.dkx * (double)kxs;
 
     if constexpr (MODE == COL_PROP) {
-        // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny).
-        // With phi = E dt: phi^2 = X0 + (c dt py)^2, X0 = (c dt)^2 (c^2 + px^2) per lane,
-        // and (a, bx, by) = sin(phi)/phi (c^2, c px, c py) dt.
-        const double cdt = c * a.dt;
-        const double X0 = cdt * cdt * (c * c + px * px);
-        const double cdtdky = cdt * a.dky;
-        const T nrm = (T)a.inv_cells;
+        // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny):
+        // the table holds (cos(E dt), sin(E dt)/E)/(nx ny) at (|kx|, |ky|) (E depends on
+        // |p| only); the matrix entries are (a, bx, by) = sin(E dt)/E (c^2, c px, c py)
+        const int ny2 = N / 2 + 1;
+        const cx<T>* kt = reinterpret_cast<const cx<T>*>(a.ktab) + (size_t)(kxs < 0 ? -kxs : kxs) * ny2;
         const T sgn = blk ? (T)-1 : (T)1;  // sign of the sigma_z term in each lane's order
-        const T ka = sgn * (T)(c * cdt * a.inv_cells);      // c^2 dt / (nx ny)
-        const T kx = (T)(cdt * px * a.inv_cells);           // c px dt / (nx ny)
-        const T ky = (T)(cdt * a.dky * a.inv_cells);        // c dky dt / (nx ny)
-        if (a.dt != 0.0) {
+        const T ka = sgn * (T)(c * c);
+        const T kx = (T)(c * px);
+        const T ky = (T)(c * a.dky);
+        asm volatile("" ::: "memory");
+        int tt = t;
+        asm volatile("" : "+v"(tt));
 #pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int kys = signed_idx(t + NT * m, N);
-                const double u = cdtdky * (double)kys;
-                T sn, cs, inv_phi;
-                kinetic_phase(fma(u, u, X0), sn, cs, inv_phi);
-                const T q = sn * inv_phi;  // sin(phi)/phi
-                block_prop(v[0][m], v[1][m], cs * nrm, q * ka, q * kx, q * ky * (T)kys);
-            }
-        } else {  // K(p, 0) = I: only the transform normalisation (phi = 0 has no 1/phi)
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                v[0][m] = scale(v[0][m], nrm);
-                v[1][m] = scale(v[1][m], nrm);
-            }
+        for (int m = 0; m < E; ++m) {
+            const int kys = signed_idx(tt + NT * m, N);
+            const cx<T> cq = kt[kys < 0 ? -kys : kys];
+            block_prop(v[0][m], v[1][m], cq.re, cq.im * ka, cq.im * kx, cq.im * ky * (T)kys);
         }
         fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
     }
@@ -477,6 +461,23 @@ __global__ void beam_tables(cx<T>* bx, cx<T>* by, BeamArgs b)
         }
         by[i] = cx<T>{y0, y1};
     }
+}
+
+// kinetic table: for |kx| <= nx/2, |ky| <= ny/2 the pair
+// (cos(E dt), sin(E dt)/E) / (nx ny) with E = c sqrt(c^2 + p^2), evaluated in
+// double (phase E dt in double, reduced in double) and rounded to T
+template <typename T>
+__global__ void kinetic_table(cx<T>* kt, KineticArgs k)
+{
+    const int nx2 = k.nx / 2 + 1, ny2 = k.ny / 2 + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx2 * ny2) return;
+    const int ix = i / ny2, iy = i - ix * ny2;
+    const double px = k.dkx * (double)ix, py = k.dky * (double)iy;
+    const double en = k.c * sqrt(k.c * k.c + px * px + py * py);
+    double s, c;
+    sincos_phase(en * k.dt, s, c);
+    kt[i] = cx<T>{(T)(c * k.inv_cells), (T)(s / en * k.inv_cells)};
 }
 
 // ---------------------------------------------------------------------------
@@ -630,6 +631,14 @@ hipError_t launch_beam_tables(void* bx, void* by, const BeamArgs& b, hipStream_t
 }
 
 template <typename T>
+hipError_t launch_kinetic_table(void* kt, const KineticArgs& k, hipStream_t st)
+{
+    const int n = (k.nx / 2 + 1) * (k.ny / 2 + 1);
+    hipLaunchKernelGGL(kinetic_table<T>, dim3((n + 255) / 256), dim3(256), 0, st, reinterpret_cast<cx<T>*>(kt), k);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_packet(void* psi, double* rownorm, const PacketArgs& e, hipStream_t st)
 {
     hipLaunchKernelGGL(packet_momentum<T>, dim3(e.ny), dim3(256), 0, st, reinterpret_cast<cx<T>*>(psi), rownorm, e);
@@ -657,5 +666,9 @@ hipError_t launch_packet(void* psi, double* rownorm, const PacketArgs& e, hipStr
     hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s)          \
     {                                                                                                        \
         return launch_packet<T>(psi, rownorm, e, s);                                                         \
+    }                                                                                                        \
+    hipError_t launch_kinetic_table_##SUF(void* kt, const KineticArgs& k, hipStream_t s)                     \
+    {                                                                                                        \
+        return launch_kinetic_table<T>(kt, k, s);                                                            \
     }                                                                                                        \
     }

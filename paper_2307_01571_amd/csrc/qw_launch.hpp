@@ -33,7 +33,8 @@ struct RowArgs {
 
 struct ColArgs {
     void* psi;
-    const void* twy;  // per-pass twiddles of the y transform (2 ny entries)
+    const void* twy;   // per-pass twiddles of the y transform (2 ny entries)
+    const void* ktab;  // COL_PROP: kinetic table, (nx/2+1) x (ny/2+1) pairs (cos(E dt), sin(E dt)/E)/(nx ny)
     int nx;
     double dkx, dky, c, dt, inv_cells;
     double* partial;  // COL_OBS: per-workgroup sums, partial_stride doubles each
@@ -44,6 +45,11 @@ struct ColArgs {
 struct BeamArgs {
     int mode, longitudinal, nx, ny;
     double x_min, y_min, lx, ly, a0, kl, w0, ux, uy;
+};
+
+struct KineticArgs {
+    int nx, ny;
+    double dkx, dky, c, dt, inv_cells;
 };
 
 struct PacketArgs {
@@ -59,7 +65,8 @@ struct PacketArgs {
     int col_blocks_##SUF(int nx, int ny);                                                 \
     hipError_t launch_twiddles_##SUF(void* tw, int n, hipStream_t s);                     \
     hipError_t launch_beam_tables_##SUF(void* bx, void* by, const BeamArgs& b, hipStream_t s); \
-    hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s);
+    hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s); \
+    hipError_t launch_kinetic_table_##SUF(void* ktab, const KineticArgs& k, hipStream_t s);
 QW_DECLARE_LAUNCHERS(f32)
 QW_DECLARE_LAUNCHERS(f64)
 #undef QW_DECLARE_LAUNCHERS

@@ -1,0 +1,107 @@
+"""GPU parity at the workloads' full sizes, through the C ABI.
+
+References:
+  * tests/golden/*.json, written by tests/golden/make_golden.py from the
+    oracle alone: the 512 x 512 runs over their full 1e4 steps and 50/100-step
+    prefixes of the 2048 x 2048 run (the full 5e4 steps would take the oracle
+    about a day), each with the final observables and a seeded sample of
+    final cells (the 64 densest cells plus 192 uniform ones);
+  * for the full 2048 x 2048, 5e4-step FP32 run: the GPU FP64 run, which the
+    prefix tests tie to the oracle on the same grid.
+Bars: FP64 sampled cells within 1e-10 relative L2 and probabilities within
+1e-12 of the oracle; FP32 probabilities within 1e-4 absolute.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2307_01571_amd import qw
+from paper_2307_01571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU (HIP device)")
+    qw.lib()
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+def workload_of(rec) -> W.Workload:
+    w = rec["workload"]
+    return W.Workload(w["name"], W.GridSpec(**w["grid"]), W.BeamSpec(**w["beam"]), W.PacketSpec(**w["packet"]),
+                      W.ObsSpec(**w["obs"]), dt=w["dt"], steps=w["steps"], t0=w["t0"], meta=w["meta"])
+
+
+def run_gpu(wl, prec, steps, t0):
+    print(f"[case] {wl.name} prec={prec} steps={steps} t0={t0}", flush=True)
+    sim = qw.Sim(wl.grid, prec, beam=wl.beam)
+    sim.init_packet(wl.packet)
+    sim.step(steps, t0, wl.dt)
+    obs = np.array(sim.observables(wl.obs))
+    return sim, obs
+
+
+def check_f64(rec):
+    wl = workload_of(rec)
+    sim, obs = run_gpu(wl, qw.QW_F64, rec["steps"], rec["t0"])
+    ref_obs = np.array(rec["observables"])
+    cells = rec["cells"]
+    ref = np.array(rec["psi_re"]) + 1j * np.array(rec["psi_im"])
+    psi = sim.state()
+    got = np.array([psi[iy, ix] for iy, ix in cells])
+    sim.close()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  sampled-cell rel L2 {err:.3e}, max |d obs| {np.max(np.abs(obs[1:] - ref_obs[1:])):.3e}, "
+          f"norm diff {abs(obs[0] - ref_obs[0]):.3e}")
+    assert err <= 1e-10
+    assert abs(obs[0] - ref_obs[0]) <= 1e-11
+    assert np.max(np.abs(obs[1:] - ref_obs[1:])) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["large_prefix0", "large_prefix_field"])
+def test_large_grid_prefix_f64_matches_oracle(name):
+    check_f64(load(name))
+
+
+@pytest.mark.parametrize("name", ["mid_w2", "mid_w4", "mid_w8"])
+def test_mid_grid_full_run_f64_matches_oracle(name):
+    check_f64(load(name))
+
+
+@pytest.mark.parametrize("name", ["mid_w2", "mid_w4", "mid_w8"])
+def test_mid_grid_full_run_f32_probabilities(name):
+    rec = load(name)
+    wl = workload_of(rec)
+    sim, obs = run_gpu(wl, qw.QW_F32, rec["steps"], rec["t0"])
+    sim.close()
+    ref = np.array(rec["observables"])
+    d = np.abs(obs[1:] - ref[1:])
+    nb = 2 * wl.obs.n_max + 1
+    flip_rel = d[3 * nb] / max(ref[1 + 3 * nb], 1e-300)
+    print(f"  FP32 vs oracle: max |dP| {d.max():.3e}, P_+1 {ref[4]:.4e} (d {d[3]:.2e}), "
+          f"P_flip {ref[1 + 3 * nb]:.4e} (rel {flip_rel:.2e}), norm drift {obs[0] - 1:.2e}")
+    assert d.max() <= 1e-4
+
+
+def test_large_grid_full_run_f32_vs_f64():
+    """The spec workload: 2048^2, 5e4 steps; FP32 against the GPU FP64 run."""
+    wl = W.large()
+    _, o64 = run_gpu(wl, qw.QW_F64, wl.steps, 0.0)
+    _, o32 = run_gpu(wl, qw.QW_F32, wl.steps, 0.0)
+    d = np.abs(o32[1:] - o64[1:])
+    nb = 2 * wl.obs.n_max + 1
+    print(f"  FP32 vs FP64 after {wl.steps} steps: max |dP| {d.max():.3e}; P_+1 {o64[4]:.4e} "
+          f"(d {d[3]:.2e}); P_flip {o64[1 + 3 * nb]:.4e} (d {d[3 * nb]:.2e}); norm drift {o32[0] - 1:.2e}")
+    assert d.max() <= 1e-4
