@@ -155,6 +155,93 @@ const char *qw_last_error(qw_ctx h);
 /* Release the context (not the caller's psi or workspace).  NULL is a no-op. */
 void qw_destroy(qw_ctx h);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent instances -- each with its own grid, field
+ * and packet, all of one precision -- advanced together.  Every pass of a
+ * step is one kernel launch over the tiles of all instances, the step loop
+ * replays a captured HIP graph, and the transform schedules are picked per
+ * line length by a built-in autotuner.  The physics of each instance is
+ * exactly that of the single-instance calls above (same kernels' bodies).
+ *
+ * Batch state: the instances' psi arrays back to back in one caller-owned
+ * device buffer, instance i at byte offset offsets[i] (256-byte aligned),
+ * each laid out as psi above.  Limits: 1 <= n <= 65535 instances; nx, ny
+ * powers of two in [64, 2048] for QW_F32 and [64, 1024] for QW_F64.
+ * The batch workspace (caller-owned device memory, 256-byte aligned) holds
+ * the tables, the work lists, the reduction scratch and one plane the size
+ * of the batch state.
+ * ------------------------------------------------------------------------- */
+typedef struct qw_batch_s *qw_batch;
+
+typedef struct {
+    qw_grid grid;
+    qw_beam beam;
+} qw_instance;
+
+/* Sizes for n instances: offsets[i] (n entries, may be NULL), total state
+ * bytes and workspace bytes (either may be NULL).  Host-only. */
+int qw_batch_layout(const qw_instance *inst, int32_t n, int64_t *offsets, size_t *state_bytes, size_t *ws_bytes);
+
+/* Validate the instances, bind the workspace and build every table on
+ * hip_stream (waits for it).  On success *out is a new batch.  The schedule
+ * variant of every length starts at 0 (the single-instance plan), the
+ * launch at one workgroup per tile with 64-step graph chunks. */
+int qw_batch_init(qw_batch *out, const qw_instance *inst, int32_t n, void *workspace, size_t ws_bytes,
+                  void *hip_stream);
+
+/* Write each instance's normalised initial packet (packets: n entries). */
+int qw_batch_init_packets(qw_batch b, void *psi, const qw_packet *packets, void *hip_stream);
+
+/* n >= 0 steps of every instance from t0 with step dt, in place, with the
+ * same sequence as qw_step_n; asynchronous.  The middle steps run as
+ * replays of a captured graph of graph_steps (column pass, row pass) pairs
+ * whose step index comes from a device counter; the rest are direct
+ * launches. */
+int qw_batch_step_n(qw_batch b, void *psi, int64_t n, double t0, double dt, void *hip_stream);
+
+/* Observables of every instance (specs: n entries, one n_max for all) into
+ * out_host: instance i at out_host[i (3B + 3)], laid out as qw_observables;
+ * out_len >= n (3B + 3).  Waits for hip_stream. */
+int qw_batch_observables(qw_batch b, const void *psi, const qw_obs_spec *specs, double *out_host, int32_t out_len,
+                         void *hip_stream);
+
+/* Schedules.  qw_batch_schedule writes the radices of variant v for line
+ * length 2^log2n into radices (up to max_radices) and returns their count
+ * (0: no such variant) or a negative error.  qw_batch_set_schedule picks
+ * variant v for the row (pass = 0) or column (pass = 1) transforms of that
+ * length in the step's middle passes. */
+int qw_batch_schedule(qw_batch b, int32_t log2n, int32_t v, int32_t *radices, int32_t max_radices);
+int qw_batch_set_schedule(qw_batch b, int32_t log2n, int32_t pass, int32_t v);
+
+/* Launch shape: wg_per_cu = 0 launches one workgroup per tile; k > 0 a
+ * persistent grid of k workgroups per compute unit that loop over the
+ * tiles (row and column pass separately); graph_steps = 0 launches every
+ * step directly. */
+int qw_batch_set_launch(qw_batch b, int32_t row_wg_per_cu, int32_t col_wg_per_cu, int32_t graph_steps);
+
+/* Autotuner: times, on a copy of psi in the workspace (psi is not
+ * modified), every schedule variant of every line length of the batch for
+ * the row and column passes, then the launch shapes, and keeps the fastest
+ * of each.  reps launches per candidate.  report (optional, report_len
+ * doubles) receives rows of 4 values (kind, a, b, microseconds per launch):
+ * kind 0 row schedule (a = log2n, b = variant), 1 column schedule,
+ * 2 row launch (a = wg_per_cu), 3 column launch; *n_rows their count.
+ * Waits for hip_stream. */
+int qw_batch_autotune(qw_batch b, const void *psi, double dt, int32_t reps, double *report, int32_t report_len,
+                      int32_t *n_rows, void *hip_stream);
+
+/* Per-kernel timing, as qw_kernel_timing / qw_kernel_times (graphs are not
+ * used while timing is on). */
+int qw_batch_kernel_timing(qw_batch b, int enable);
+int qw_batch_kernel_times(qw_batch b, double *out, int32_t out_len, void *hip_stream);
+
+/* Message of the last failure on b (or of the last failed qw_batch_init or
+ * qw_batch_layout when b is NULL). */
+const char *qw_batch_last_error(qw_batch b);
+
+/* Release the batch (graphs, events, host memory; not psi or workspace). */
+void qw_batch_destroy(qw_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,15 @@ OUT = os.path.join(HERE, "libqw.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
-SOURCES = ["qw_kernels_f32.hip", "qw_kernels_f64.hip", "qw_common.hip", "qw_api.cpp"]
+# the slowest translation units first
+SOURCES = ["qw_batch_f32.hip", "qw_kernels_f32.hip", "qw_batch_f64.hip", "qw_kernels_f64.hip", "qw_common.hip",
+           "qw_api.cpp", "qw_batch.cpp"]
+# per-file flags: the batched kernels are built without machine loop-invariant
+# code motion (see qw_batch_f32.hip)
+SOURCE_FLAGS = {
+    "qw_batch_f32.hip": ["-mllvm", "-disable-machine-licm"],
+    "qw_batch_f64.hip": ["-mllvm", "-disable-machine-licm"],
+}
 COMMON_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # packed FP32 instructions stay off (see the kernels' build notes)
@@ -38,7 +46,7 @@ def hipcc() -> str:
 
 def _compile(src: str, extra=(), build_dir=BUILD_DIR) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *COMMON_FLAGS, *SOURCE_FLAGS.get(src, []), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,7 +59,7 @@ def build(verbose: bool = False, extra_flags=(), out: str = OUT) -> str:
     """Compile and link; extra_flags (e.g. -D tuning macros) and out allow variant builds."""
     build_dir = BUILD_DIR if out == OUT else out + ".objs"
     os.makedirs(build_dir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
         objs = list(ex.map(lambda s: _compile(s, tuple(extra_flags), build_dir), SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

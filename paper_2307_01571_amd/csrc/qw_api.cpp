@@ -14,18 +14,14 @@
 #include <string>
 #include <vector>
 
+#include "qw_host.hpp"
 #include "qw_launch.hpp"
 
 namespace {
 
-constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr int kMaxNmax = 16;
-constexpr int kPartialStride = 3 * (2 * kMaxNmax + 1) + 3;  // doubles per column-pass workgroup
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-bool is_pow2_in_range(int n) { return n >= 8 && n <= 4096 && (n & (n - 1)) == 0; }
+using qwh::align_up;
+using qwh::kAlign;
+using qwh::kPartialStride;
 
 // workspace layout (byte offsets from the start, each 256-aligned)
 struct Layout {
@@ -112,22 +108,12 @@ int hip_fail(qw_ctx h, hipError_t e, const char* what)
     return fail(h, QW_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-bool finite_all(std::initializer_list<double> v)
-{
-    for (double x : v)
-        if (!std::isfinite(x)) return false;
-    return true;
-}
-
 int check_grid(const qw_grid* g)
 {
     if (!g) return fail(nullptr, QW_E_ARG, "grid is NULL");
-    if (!is_pow2_in_range(g->nx) || !is_pow2_in_range(g->ny))
-        return fail(nullptr, QW_E_SIZE, "nx=%d ny=%d: each must be a power of two in [8, 4096]", g->nx, g->ny);
-    if (g->precision != QW_F32 && g->precision != QW_F64)
-        return fail(nullptr, QW_E_ARG, "precision %d is neither QW_F64 nor QW_F32", g->precision);
-    if (!finite_all({g->x_min, g->y_min, g->lx, g->ly, g->c}) || !(g->lx > 0) || !(g->ly > 0) || !(g->c > 0))
-        return fail(nullptr, QW_E_ARG, "box and c must be finite with lx, ly, c > 0");
+    std::string msg;
+    const int rc = qwh::check_grid(*g, 8, 4096, &msg);
+    if (rc != QW_OK) return fail(nullptr, rc, "%s", msg.c_str());
     return QW_OK;
 }
 
@@ -178,21 +164,7 @@ hipError_t timed(qw_ctx h, int kind, hipStream_t s, F&& launch)
 int ensure_tables(qw_ctx h, hipStream_t s)
 {
     if (!h->tables_dirty) return QW_OK;
-    const qw_beam& b = h->b;
-    qw::BeamArgs a{};
-    a.mode = b.mode;
-    a.longitudinal = b.longitudinal;
-    a.nx = h->g.nx;
-    a.ny = h->g.ny;
-    a.x_min = h->g.x_min;
-    a.y_min = h->g.y_min;
-    a.lx = h->g.lx;
-    a.ly = h->g.ly;
-    a.a0 = b.a0;
-    a.kl = b.mode == QW_BEAM_STANDING_PARAXIAL ? 2.0 * kPi / b.lambda_l : 0.0;
-    a.w0 = b.w0;
-    a.ux = b.ux;
-    a.uy = b.uy;
+    const qw::BeamArgs a = qwh::beam_args(h->g, h->b);
     void* bx = h->ws + h->lay.bx;
     void* by = h->ws + h->lay.by;
     hipError_t e = f32(h) ? qw::launch_beam_tables_f32(bx, by, a, s) : qw::launch_beam_tables_f64(bx, by, a, s);
@@ -205,14 +177,7 @@ int ensure_tables(qw_ctx h, hipStream_t s)
 int ensure_kinetic_table(qw_ctx h, double dt, hipStream_t s)
 {
     if (h->ktab_valid && h->ktab_dt == dt) return QW_OK;
-    qw::KineticArgs k{};
-    k.nx = h->g.nx;
-    k.ny = h->g.ny;
-    k.dkx = 2.0 * kPi / h->g.lx;
-    k.dky = 2.0 * kPi / h->g.ly;
-    k.c = h->g.c;
-    k.dt = dt;
-    k.inv_cells = 1.0 / ((double)h->g.nx * (double)h->g.ny);
+    const qw::KineticArgs k = qwh::kinetic_args(h->g, dt);
     void* kt = h->ws + h->lay.ktab;
     hipError_t e = f32(h) ? qw::launch_kinetic_table_f32(kt, k, s) : qw::launch_kinetic_table_f64(kt, k, s);
     if (e != hipSuccess) return hip_fail(h, e, "kinetic table kernel");
@@ -231,15 +196,7 @@ qw::RowArgs row_args(qw_ctx h, const void* src, void* dst)
     a.beam_y = h->ws + h->lay.by;
     a.rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
     a.scale_src = reinterpret_cast<const double*>(h->ws + h->lay.scalars);
-    const qw_beam& b = h->b;
-    a.beam_mode = h->beam_set ? b.mode : QW_BEAM_NONE;
-    if (b.mode == QW_BEAM_STANDING_PARAXIAL) {
-        a.omega = h->g.c * 2.0 * kPi / b.lambda_l;
-        a.t_ramp = b.ramp_periods * b.lambda_l / h->g.c;
-        a.ramp_k = a.t_ramp > 0 ? kPi / (2.0 * a.t_ramp) : 0.0;
-    }
-    a.c = h->g.c;
-    a.ny = h->g.ny;
+    qwh::row_field(h->g, h->b, h->beam_set, &a);
     return a;
 }
 
@@ -249,13 +206,8 @@ qw::ColArgs col_args(qw_ctx h, void* psi)
     a.psi = psi;
     a.twy = h->ws + h->lay.twy;
     a.ktab = h->ws + h->lay.ktab;
-    a.nx = h->g.nx;
-    a.dkx = 2.0 * kPi / h->g.lx;
-    a.dky = 2.0 * kPi / h->g.ly;
-    a.c = h->g.c;
-    a.inv_cells = 1.0 / ((double)h->g.nx * (double)h->g.ny);
+    qwh::col_grid(h->g, &a);
     a.partial = reinterpret_cast<double*>(h->ws + h->lay.partial);
-    a.partial_stride = kPartialStride;
     return a;
 }
 
@@ -323,15 +275,9 @@ int qw_set_beam(qw_ctx h, const qw_beam* b)
 {
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
     if (!b) return fail(h, QW_E_ARG, "beam is NULL");
-    if (b->mode != QW_BEAM_NONE && b->mode != QW_BEAM_STANDING_PARAXIAL && b->mode != QW_BEAM_UNIFORM)
-        return fail(h, QW_E_ARG, "unknown beam mode %d", b->mode);
-    if (b->mode == QW_BEAM_STANDING_PARAXIAL) {
-        if (!finite_all({b->a0, b->lambda_l, b->w0, b->ramp_periods}) || !(b->lambda_l > 0) || !(b->w0 > 0) ||
-            b->ramp_periods < 0)
-            return fail(h, QW_E_ARG, "standing wave needs finite a0, lambda_l > 0, w0 > 0, ramp_periods >= 0");
-    }
-    if (b->mode == QW_BEAM_UNIFORM && !finite_all({b->ux, b->uy}))
-        return fail(h, QW_E_ARG, "uniform field must be finite");
+    std::string msg;
+    const int rc = qwh::check_beam(*b, &msg);
+    if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
     h->b = *b;
     h->beam_set = true;
     h->tables_dirty = true;
@@ -342,24 +288,11 @@ int qw_init_packet(qw_ctx h, void* psi, const qw_packet* e, void* hip_stream)
 {
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
     if (!psi || !e) return fail(h, QW_E_ARG, "psi or packet is NULL");
-    if (!finite_all({e->p0x, e->p0y, e->x0, e->y0, e->sigma_x}) || !(e->sigma_x > 0) ||
-        (e->spin != 1 && e->spin != -1))
-        return fail(h, QW_E_ARG, "packet needs finite values, sigma_x > 0 and spin = +1 or -1");
+    std::string msg;
+    const int rc = qwh::check_packet(*e, &msg);
+    if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
     hipStream_t s = as_stream(hip_stream);
-    qw::PacketArgs p{};
-    p.nx = h->g.nx;
-    p.ny = h->g.ny;
-    p.spin = e->spin;
-    p.dkx = 2.0 * kPi / h->g.lx;
-    p.dky = 2.0 * kPi / h->g.ly;
-    p.c = h->g.c;
-    p.p0x = e->p0x;
-    p.p0y = e->p0y;
-    p.x0 = e->x0;
-    p.y0 = e->y0;
-    p.sigma_x = e->sigma_x;
-    p.x_min = h->g.x_min;
-    p.y_min = h->g.y_min;
+    const qw::PacketArgs p = qwh::packet_args(h->g, *e);
     double* rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
     double* total = reinterpret_cast<double*>(h->ws + h->lay.scalars);
     hipError_t err = f32(h) ? qw::launch_packet_f32(psi, rownorm, p, s) : qw::launch_packet_f64(psi, rownorm, p, s);
@@ -375,20 +308,13 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
     if (!psi) return fail(h, QW_E_ARG, "psi is NULL");
     if (n < 0) return fail(h, QW_E_ARG, "n = %lld is negative", (long long)n);
-    if (!finite_all({t0, dt})) return fail(h, QW_E_ARG, "t0 and dt must be finite");
+    if (!qwh::finite_all({t0, dt})) return fail(h, QW_E_ARG, "t0 and dt must be finite");
     if (!h->beam_set) return fail(h, QW_E_STATE, "qw_set_beam has not been called");
     if (n == 0) return QW_OK;
-    if (h->b.mode == QW_BEAM_STANDING_PARAXIAL) {
-        // the in-kernel phase reduction is exact for |w t| < 2^20 pi/2
-        const double om = h->g.c * 2.0 * kPi / h->b.lambda_l;
-        const double tmax = std::fmax(std::fabs(t0), std::fabs(t0 + (double)n * dt));
-        if (om * tmax > 1.6e6) return fail(h, QW_E_ARG, "|omega t| = %g exceeds 1.6e6", om * tmax);
-    }
-    // |E dt| must stay inside the exact range of the in-kernel phase reduction
     {
-        const double px = 0.5 * h->g.nx * 2.0 * kPi / h->g.lx, py = 0.5 * h->g.ny * 2.0 * kPi / h->g.ly;
-        const double emax = h->g.c * std::sqrt(h->g.c * h->g.c + px * px + py * py);
-        if (emax * std::fabs(dt) > 1.6e6) return fail(h, QW_E_ARG, "|E dt| = %g exceeds 1.6e6", emax * std::fabs(dt));
+        std::string msg;
+        const int rc = qwh::check_phases(h->g, h->b, true, n, t0, dt, &msg);
+        if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
     }
     hipStream_t s = as_stream(hip_stream);
     int rc = ensure_tables(h, s);
@@ -425,10 +351,11 @@ int qw_observables(qw_ctx h, const void* psi, const qw_obs_spec* o, double* out_
 {
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
     if (!psi || !o || !out_host) return fail(h, QW_E_ARG, "psi, spec or out is NULL");
-    if (o->n_max < 0 || o->n_max > kMaxNmax) return fail(h, QW_E_ARG, "n_max must be in [0, %d]", kMaxNmax);
-    if (o->band_half_idx <= 0 || o->window_idx < 0 || o->window_idx >= o->band_half_idx)
-        return fail(h, QW_E_ARG, "need band_half_idx > 0 and 0 <= window_idx < band_half_idx");
-    if (o->spin0 != 1 && o->spin0 != -1) return fail(h, QW_E_ARG, "spin0 must be +1 or -1");
+    {
+        std::string msg;
+        const int rc = qwh::check_obs(*o, &msg);
+        if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
+    }
     const int nb = 2 * o->n_max + 1;
     if (out_len < 3 * nb + 3) return fail(h, QW_E_ARG, "out_len %d < %d", out_len, 3 * nb + 3);
     hipStream_t s = as_stream(hip_stream);

@@ -170,17 +170,18 @@ __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k :
 // ---------------------------------------------------------------------------
 // row pass
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_ROW))) void row_pass(RowArgs a)
+// One tile of RPW rows of length N (transform with E elements per lane and
+// the radix schedule SCH, LDS stride LL per lane group), threads
+// 0 .. RPW 2 N/E - 1.  lds holds RPW 2 LL elements.
+template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE>
+__device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds, int tid)
 {
-    using S = shape<T, N>;
-    constexpr int E = S::E, NT = S::NT, L = S::L, RPW = S::RPW, LL = S::LLR;
-    __shared__ cx<T> lds[RPW * 2 * LL];
-    const int blk = threadIdx.x & 1;  // 0: (psi1, psi4), 1: (psi2, psi3)
-    const int q = threadIdx.x >> 1;
+    constexpr int NT = N / E, L = 2 * NT;
+    const int blk = tid & 1;  // 0: (psi1, psi4), 1: (psi2, psi3)
+    const int q = tid >> 1;
     const int s = q / NT;
     const int t = q - s * NT;
-    const int y = blockIdx.x * RPW + s;
+    const int y = tile * RPW + s;
     const bool live = y < a.ny;
     cx<T>* lb = lds + (2 * s + blk) * LL;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twx);
@@ -209,19 +210,19 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
             for (int c = 0; c < 2; ++c)
                 acc += (double)v[c][m].re * (double)v[c][m].re + (double)v[c][m].im * (double)v[c][m].im;
         double* red = reinterpret_cast<double*>(lds);
-        red[threadIdx.x] = acc;
+        red[tid] = acc;
         __syncthreads();
-        const int l = threadIdx.x - s * L;
+        const int l = tid - s * L;
         for (int w = L / 2; w > 0; w >>= 1) {
-            if (l < w) red[threadIdx.x] += red[threadIdx.x + w];
+            if (l < w) red[tid] += red[tid + w];
             __syncthreads();
         }
-        if (l == 0 && live) a.rownorm[y] = red[threadIdx.x];
+        if (l == 0 && live) a.rownorm[y] = red[tid];
         __syncthreads();
     }
 
     if constexpr (MODE == ROW_MID || MODE == ROW_LAST || MODE == ROW_INV_SCALE)
-        fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
+        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
 
     if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_LAST) {
         // interaction propagator V(t, tau) with A evaluated from the field tables;
@@ -248,30 +249,34 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
     }
 
     if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_FWD_NORM)
-        fft<T, N, E, 2, false>(typename plan<T, N>::S{}, v, t, tw, lb);
+        fft<T, N, E, 2, false>(SCH{}, v, t, tw, lb);
 
 #pragma unroll
     for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rd, lane, m * NT * CB);
 }
 
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_ROW))) void row_pass(RowArgs a)
+{
+    using S = shape<T, N>;
+    __shared__ cx<T> lds[S::RPW * 2 * S::LLR];
+    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE>(a, blockIdx.x, lds, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // column pass
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE>
-__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_COL))) void col_pass(ColArgs a)
+// One tile of TX columns of length N, threads 0 .. TX 2 N/E - 1; lds holds
+// TX 2 LL elements.
+template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE>
+__device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds, int tid)
 {
-    using S = shape<T, N>;
-    constexpr int E = S::E, NT = S::NT, TX = S::TX, LL = S::LLC;
-    __shared__ cx<T> lds[TX * 2 * LL];
+    constexpr int NT = N / E, L = 2 * NT;
     // lane order: block fastest, then the column within the tile, then t, so
     // a wave reads TX whole cells of each of several rows
-    const int blk = threadIdx.x & 1;
-    const int cl = (threadIdx.x >> 1) % TX;
-    const int t = (threadIdx.x >> 1) / TX;
-    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-    // give each XCD a contiguous run of tiles -- neighbouring tiles share
-    // cache lines and then meet in the same L2
-    const int tile = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const int blk = tid & 1;
+    const int cl = (tid >> 1) % TX;
+    const int t = (tid >> 1) / TX;
     const int x = tile * TX + cl;
     const bool live = x < a.nx;
     cx<T>* lb = lds + (2 * cl + blk) * LL;
@@ -291,9 +296,9 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     }
 
     if constexpr (MODE == COL_INV) {
-        fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
+        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
     } else {
-        fft<T, N, E, 2, false>(typename plan<T, N>::S{}, v, t, tw, lb);
+        fft<T, N, E, 2, false>(SCH{}, v, t, tw, lb);
     }
 
     const double c = a.c;
@@ -319,7 +324,7 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
             const cx<T> cq = kt[kys < 0 ? -kys : kys];
             block_prop(v[0][m], v[1][m], cq.re, cq.im * ka, cq.im * kx, cq.im * ky * (T)kys);
         }
-        fft<T, N, E, 2, true>(typename plan<T, N>::S{}, v, t, tw, lb);
+        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
     }
 
     if constexpr (MODE == COL_PROP || MODE == COL_INV) {
@@ -358,20 +363,20 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
         }
         __syncthreads();  // LDS reused for the reduction
         double* red = reinterpret_cast<double*>(lds);
-        constexpr int nthr = TX * S::L;
-        red[threadIdx.x] = sw;
-        red[nthr + threadIdx.x] = sp;
-        red[2 * nthr + threadIdx.x] = sm;
+        constexpr int nthr = TX * L;
+        red[tid] = sw;
+        red[nthr + tid] = sp;
+        red[2 * nthr + tid] = sm;
         __syncthreads();
         // fold the lanes of each column (index = (t TX + cl) 2 + blk) onto t = 0, blk = 0
         for (int w = nthr / 2; w >= 2 * TX; w >>= 1) {
-            if (threadIdx.x < w) {
+            if (tid < w) {
 #pragma unroll
-                for (int q = 0; q < 3; ++q) red[q * nthr + threadIdx.x] += red[q * nthr + threadIdx.x + w];
+                for (int q = 0; q < 3; ++q) red[q * nthr + tid] += red[q * nthr + tid + w];
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             const int nb = 2 * a.n_max + 1;
             double* out = a.partial + (size_t)tile * a.partial_stride;
             for (int i = 0; i < 3 * nb + 3; ++i) out[i] = 0.0;
@@ -400,6 +405,18 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     }
 }
 
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_COL))) void col_pass(ColArgs a)
+{
+    using S = shape<T, N>;
+    __shared__ cx<T> lds[S::TX * 2 * S::LLC];
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+    // give each XCD a contiguous run of tiles -- neighbouring tiles share
+    // cache lines and then meet in the same L2
+    const int tile = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE>(a, tile, lds, threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // tables
 // ---------------------------------------------------------------------------
@@ -426,11 +443,11 @@ __device__ void pass_twiddle(sched<R...>, cx<T>* tw, int i)
     tw[i] = cx<T>{(T)v.re, (T)v.im};
 }
 
-template <typename T, int N>
+template <typename T, int N, typename SCH = typename plan<T, N>::S>
 __global__ void twiddle_table(cx<T>* tw)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 2 * N) pass_twiddle<T>(typename plan<T, N>::S{}, tw, i);
+    if (i < 2 * N) pass_twiddle<T>(SCH{}, tw, i);
 }
 
 // field tables: beam_x[i] = (X0, X1) and beam_y[j] = (Y0, Y1) with

@@ -57,6 +57,51 @@ struct PacketArgs {
     double dkx, dky, c, p0x, p0y, x0, y0, sigma_x, x_min, y_min;
 };
 
+// ---------------------------------------------------------------------------
+// Batched form: independent instances, each with its own grid, field and
+// packet, advanced by one launch per pass.  A launch walks a list of work
+// items (instance, tile); every tile is one 256-thread workgroup's worth of
+// lines of that instance, whatever its length.
+// ---------------------------------------------------------------------------
+constexpr int kBatchThreads = 256;
+constexpr int kBatchMaxVariants = 4;  // schedule variants per transform length
+
+struct BatchInst {
+    RowArgs row;           // row pass arguments (state pointers and time set per launch)
+    ColArgs col;           // column pass arguments (state pointer set per launch)
+    const void* tw_row;    // twiddles of the tuned schedules used by ROW_MID ...
+    const void* tw_col;    // ... and COL_PROP (the other modes use the default plan's)
+    double* scalars;       // [0] packet norm, [8 ..) observables
+    long long off;         // byte offset of the instance's state from the batch base
+    int lgx, lgy;          // log2 nx, log2 ny
+    int row_var, col_var;  // tuned schedule variants (0 = default plan)
+    int ntile_col;         // column tiles (partials for the observables)
+    int pad_;
+};
+
+// Device-resident time of a batched propagation: V is taken at t0 + k dt
+// with k = (use_counter ? k_base : 0) + j.  A graph-captured chunk of steps
+// reads k_base and advances it by its length at its end, so one captured
+// chunk replays for every chunk of a run.
+struct BatchTime {
+    double t0, dt;
+    long long k_base;
+    long long pad_;
+};
+
+struct BatchLaunch {
+    const BatchInst* __restrict__ inst;
+    const uint32_t* __restrict__ items;  // (instance << 16) | tile
+    int n_items;
+    int j;            // step index (plus k_base when use_counter)
+    int use_counter;
+    int pad_;
+    char* src;        // state bases; dst may equal src
+    char* dst;
+    const BatchTime* time;
+    double tau_frac;
+};
+
 // Per-precision entry points (qw_kernels_f32.hip, qw_kernels_f64.hip).
 // n is the transform length (nx for rows, ny for columns).
 #define QW_DECLARE_LAUNCHERS(SUF)                                                          \
@@ -66,7 +111,15 @@ struct PacketArgs {
     hipError_t launch_twiddles_##SUF(void* tw, int n, hipStream_t s);                     \
     hipError_t launch_beam_tables_##SUF(void* bx, void* by, const BeamArgs& b, hipStream_t s); \
     hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s); \
-    hipError_t launch_kinetic_table_##SUF(void* ktab, const KineticArgs& k, hipStream_t s);
+    hipError_t launch_kinetic_table_##SUF(void* ktab, const KineticArgs& k, hipStream_t s);          \
+    /* batched form (qw_batch_*.hip): lengths 2^lg, lg_min <= lg <= lg_max; schedule variant v */  \
+    int batch_lg_min_##SUF();                                                                    \
+    int batch_lg_max_##SUF();                                                                    \
+    int batch_variant_##SUF(int lg, int v, int* radices, int max_radices);                       \
+    int batch_tiles_##SUF(int lg);                                                               \
+    hipError_t launch_batch_twiddles_##SUF(void* tw, int lg, int v, hipStream_t s);              \
+    hipError_t launch_batch_row_##SUF(int mode, int grid, bool persist, const BatchLaunch& b, hipStream_t s); \
+    hipError_t launch_batch_col_##SUF(int mode, int grid, bool persist, const BatchLaunch& b, hipStream_t s);
 QW_DECLARE_LAUNCHERS(f32)
 QW_DECLARE_LAUNCHERS(f64)
 #undef QW_DECLARE_LAUNCHERS
@@ -77,5 +130,12 @@ hipError_t launch_sum_rows(const double* rownorm, int ny, double* out, hipStream
 // observables: results[0..3B+3) from the row norms and the column partials
 hipError_t launch_obs_finish(const double* rownorm, int ny, const double* partial, int nblocks, int stride,
                              int n_max, double* results, hipStream_t s);
+// batched: per instance, scalars[0] = sum of its row norms
+hipError_t launch_batch_sum_rows(const BatchInst* inst, int n, hipStream_t s);
+// batched: per instance, scalars[8 ..] = observables from its rows and column partials
+hipError_t launch_batch_obs_finish(const BatchInst* inst, int n, int stride, int n_max, hipStream_t s);
+// batched time: set (t0, dt, k_base), or advance k_base
+hipError_t launch_batch_set_time(BatchTime* t, double t0, double dt, long long k, hipStream_t s);
+hipError_t launch_batch_advance(BatchTime* t, long long steps, hipStream_t s);
 
 }  // namespace qw

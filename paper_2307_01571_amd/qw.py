@@ -33,7 +33,12 @@ QW_BEAM_STANDING_PARAXIAL = 1
 QW_BEAM_UNIFORM = 2
 
 EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_init_packet", "qw_step_n",
-            "qw_observables", "qw_kernel_timing", "qw_kernel_times", "qw_last_error", "qw_destroy")
+            "qw_observables", "qw_kernel_timing", "qw_kernel_times", "qw_last_error", "qw_destroy",
+            "qw_batch_layout", "qw_batch_init", "qw_batch_init_packets", "qw_batch_step_n",
+            "qw_batch_observables", "qw_batch_schedule", "qw_batch_set_schedule", "qw_batch_set_launch",
+            "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
+            "qw_batch_destroy")
+_NO_STATUS = ("qw_last_error", "qw_destroy", "qw_batch_last_error", "qw_batch_destroy")
 
 
 class qw_grid(ctypes.Structure):
@@ -57,6 +62,10 @@ class qw_packet(ctypes.Structure):
 class qw_obs_spec(ctypes.Structure):
     _fields_ = [("band_ref_idx", ctypes.c_int32), ("band_half_idx", ctypes.c_int32),
                 ("window_idx", ctypes.c_int32), ("n_max", ctypes.c_int32), ("spin0", ctypes.c_int32)]
+
+
+class qw_instance(ctypes.Structure):
+    _fields_ = [("grid", qw_grid), ("beam", qw_beam)]
 
 
 _lib = None
@@ -84,8 +93,26 @@ def lib():
     L.qw_last_error.restype = ctypes.c_char_p
     L.qw_destroy.argtypes = [vp]
     L.qw_destroy.restype = None
+    ip = ctypes.POINTER(qw_instance)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    L.qw_batch_layout.argtypes = [ip, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), szp, szp]
+    L.qw_batch_init.argtypes = [ctypes.POINTER(vp), ip, ctypes.c_int32, vp, ctypes.c_size_t, vp]
+    L.qw_batch_init_packets.argtypes = [vp, vp, ctypes.POINTER(qw_packet), vp]
+    L.qw_batch_step_n.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, vp]
+    L.qw_batch_observables.argtypes = [vp, vp, ctypes.POINTER(qw_obs_spec), dp, ctypes.c_int32, vp]
+    L.qw_batch_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32]
+    L.qw_batch_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.qw_batch_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.qw_batch_autotune.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int32, dp, ctypes.c_int32, i32p, vp]
+    L.qw_batch_kernel_timing.argtypes = [vp, ctypes.c_int]
+    L.qw_batch_kernel_times.argtypes = [vp, dp, ctypes.c_int32, vp]
+    L.qw_batch_last_error.argtypes = [vp]
+    L.qw_batch_last_error.restype = ctypes.c_char_p
+    L.qw_batch_destroy.argtypes = [vp]
+    L.qw_batch_destroy.restype = None
     for name in EXPORTED:
-        if name not in ("qw_last_error", "qw_destroy"):
+        if name not in _NO_STATUS:
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -159,6 +186,108 @@ def qw_destroy(ctx: int) -> None:
     lib().qw_destroy(ctypes.c_void_p(ctx))
 
 
+# ---- batched form -----------------------------------------------------------
+class QWBatchError(QWError):
+    pass
+
+
+def _bcheck(rc: int, b=None):
+    if rc != QW_OK:
+        raise QWBatchError(rc, qw_batch_last_error(b))
+
+
+def _instances(inst):
+    arr = (qw_instance * len(inst))(*inst)
+    return arr
+
+
+def qw_batch_layout(inst):
+    """(offsets, state_bytes, ws_bytes) for a list of qw_instance."""
+    n = len(inst)
+    arr = _instances(inst)
+    offs = (ctypes.c_int64 * max(n, 1))()
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _bcheck(lib().qw_batch_layout(arr, n, offs, ctypes.byref(sb), ctypes.byref(wb)))
+    return [int(v) for v in offs[:n]], sb.value, wb.value
+
+
+def qw_batch_init(inst, workspace_ptr: int, ws_bytes: int, stream: int) -> int:
+    h = ctypes.c_void_p()
+    arr = _instances(inst)
+    _bcheck(lib().qw_batch_init(ctypes.byref(h), arr, len(inst), ctypes.c_void_p(workspace_ptr), ws_bytes,
+                                ctypes.c_void_p(stream)))
+    return h.value
+
+
+def qw_batch_init_packets(b: int, psi_ptr: int, packets, stream: int) -> None:
+    arr = (qw_packet * len(packets))(*packets)
+    _bcheck(lib().qw_batch_init_packets(ctypes.c_void_p(b), ctypes.c_void_p(psi_ptr), arr,
+                                        ctypes.c_void_p(stream)), b)
+
+
+def qw_batch_step_n(b: int, psi_ptr: int, n: int, t0: float, dt: float, stream: int) -> None:
+    _bcheck(lib().qw_batch_step_n(ctypes.c_void_p(b), ctypes.c_void_p(psi_ptr), int(n), float(t0), float(dt),
+                                  ctypes.c_void_p(stream)), b)
+
+
+def qw_batch_observables(b: int, psi_ptr: int, specs, stream: int, check: bool = True):
+    n = len(specs)
+    per = 3 * (2 * specs[0].n_max + 1) + 3
+    arr = (qw_obs_spec * n)(*specs)
+    out = (ctypes.c_double * (per * n))()
+    rc = lib().qw_batch_observables(ctypes.c_void_p(b), ctypes.c_void_p(psi_ptr), arr, out, per * n,
+                                    ctypes.c_void_p(stream))
+    if check:
+        _bcheck(rc, b)
+    vals = [float(v) for v in out]
+    return rc, [vals[i * per:(i + 1) * per] for i in range(n)]
+
+
+def qw_batch_schedule(b: int, log2n: int, v: int):
+    r = (ctypes.c_int32 * 16)()
+    cnt = lib().qw_batch_schedule(ctypes.c_void_p(b), int(log2n), int(v), r, 16)
+    if cnt < 0:
+        _bcheck(cnt, b)
+    return [int(x) for x in r[:cnt]]
+
+
+def qw_batch_set_schedule(b: int, log2n: int, pass_: int, v: int) -> None:
+    _bcheck(lib().qw_batch_set_schedule(ctypes.c_void_p(b), int(log2n), int(pass_), int(v)), b)
+
+
+def qw_batch_set_launch(b: int, row_wg_per_cu: int, col_wg_per_cu: int, graph_steps: int) -> None:
+    _bcheck(lib().qw_batch_set_launch(ctypes.c_void_p(b), int(row_wg_per_cu), int(col_wg_per_cu),
+                                      int(graph_steps)), b)
+
+
+def qw_batch_autotune(b: int, psi_ptr: int, dt: float, reps: int, stream: int, max_rows: int = 256):
+    rep = (ctypes.c_double * (4 * max_rows))()
+    nr = ctypes.c_int32()
+    _bcheck(lib().qw_batch_autotune(ctypes.c_void_p(b), ctypes.c_void_p(psi_ptr), float(dt), int(reps), rep,
+                                    4 * max_rows, ctypes.byref(nr), ctypes.c_void_p(stream)), b)
+    rows = min(nr.value, max_rows)
+    return [tuple(float(v) for v in rep[4 * i:4 * i + 4]) for i in range(rows)]
+
+
+def qw_batch_kernel_timing(b: int, enable: bool) -> None:
+    _bcheck(lib().qw_batch_kernel_timing(ctypes.c_void_p(b), int(bool(enable))), b)
+
+
+def qw_batch_kernel_times(b: int, stream: int):
+    out = (ctypes.c_double * 4)()
+    _bcheck(lib().qw_batch_kernel_times(ctypes.c_void_p(b), out, 4, ctypes.c_void_p(stream)), b)
+    return [float(v) for v in out]
+
+
+def qw_batch_last_error(b=None) -> str:
+    s = lib().qw_batch_last_error(ctypes.c_void_p(b) if b else None)
+    return s.decode() if s else ""
+
+
+def qw_batch_destroy(b: int) -> None:
+    lib().qw_batch_destroy(ctypes.c_void_p(b))
+
+
 # ---- convenience owner of device tensors ---------------------------------
 def unpack_observables(out, n_max: int) -> dict:
     nb = 2 * n_max + 1
@@ -220,6 +349,95 @@ class Sim:
         if self.ctx:
             qw_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _grid_struct(grid, precision: int) -> qw_grid:
+    return qw_grid(grid.nx, grid.ny, grid.x_min, grid.y_min, grid.lx, grid.ly, grid.c, precision)
+
+
+def _beam_struct(b) -> qw_beam:
+    return qw_beam(b.mode, b.a0, b.lambda_l, b.w0, b.ramp_periods, b.longitudinal, b.ux, b.uy)
+
+
+class Batch:
+    """Batch state and workspace tensors on one device, plus the batch handle.
+
+    instances: a list of (grid, beam) pairs (the dataclasses of ``workloads``);
+    all instances share ``precision``.  ``psi`` is one uint8 tensor holding
+    every instance's state at its offset; ``state(i)`` copies one out.
+    """
+
+    def __init__(self, instances, precision: int = QW_F32, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.grids = [g for g, _ in instances]
+        self.inst = [qw_instance(_grid_struct(g, precision), _beam_struct(b)) for g, b in instances]
+        self.offsets, self.state_bytes, ws_bytes = qw_batch_layout(self.inst)
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        self.psi = torch.zeros(self.state_bytes, dtype=torch.uint8, device=self.device)
+        self.b = qw_batch_init(self.inst, self.ws.data_ptr(), ws_bytes, self.stream())
+        self.cdtype = torch.complex64 if precision == QW_F32 else torch.complex128
+
+    def __len__(self):
+        return len(self.inst)
+
+    def stream(self) -> int:
+        with self.torch.cuda.device(self.device):
+            return self.torch.cuda.current_stream().cuda_stream
+
+    def init_packets(self, packets) -> None:
+        qw_batch_init_packets(self.b, self.psi.data_ptr(),
+                              [qw_packet(p.p0x, p.p0y, p.x0, p.y0, p.sigma_x, p.spin) for p in packets],
+                              self.stream())
+
+    def step(self, n: int, t0: float, dt: float) -> None:
+        qw_batch_step_n(self.b, self.psi.data_ptr(), n, t0, dt, self.stream())
+
+    def observables(self, specs, check: bool = True):
+        s = [qw_obs_spec(o.band_ref_idx, o.band_half_idx, o.window_idx, o.n_max, o.spin0) for o in specs]
+        rc, out = qw_batch_observables(self.b, self.psi.data_ptr(), s, self.stream(), check=check)
+        return out if check else (rc, out)
+
+    def view(self, i: int):
+        """Device tensor view (ny, nx, 4) of instance i's state."""
+        g = self.grids[i]
+        esize = 8 if self.precision == QW_F32 else 16
+        nbytes = g.nx * g.ny * 4 * esize
+        raw = self.psi[self.offsets[i]:self.offsets[i] + nbytes]
+        return raw.view(self.cdtype).view(g.ny, g.nx, 4)
+
+    def state(self, i: int):
+        """Host copy of instance i's psi as a numpy complex128 array."""
+        self.torch.cuda.synchronize(self.device)
+        return self.view(i).detach().cpu().to(self.torch.complex128).numpy()
+
+    def load(self, i: int, psi_host) -> None:
+        self.view(i).copy_(self.torch.as_tensor(psi_host).to(self.cdtype).to(self.device))
+
+    def schedule(self, log2n: int, v: int):
+        return qw_batch_schedule(self.b, log2n, v)
+
+    def set_schedule(self, log2n: int, pass_: int, v: int) -> None:
+        qw_batch_set_schedule(self.b, log2n, pass_, v)
+
+    def set_launch(self, row_wg_per_cu: int = 0, col_wg_per_cu: int = 0, graph_steps: int = 64) -> None:
+        qw_batch_set_launch(self.b, row_wg_per_cu, col_wg_per_cu, graph_steps)
+
+    def autotune(self, dt: float, reps: int = 20):
+        return qw_batch_autotune(self.b, self.psi.data_ptr(), dt, reps, self.stream())
+
+    def close(self) -> None:
+        if self.b:
+            qw_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -145,6 +145,33 @@ def large() -> Workload:
     return Workload("grid2048_box64_w16_a0.5_5e4steps", g, b, p, obs_for(g, p), steps=50_000)
 
 
+def batch_instances(seed: int = 0, count: int = 96, sizes=(256, 512, 1024), steps: int = 20_000,
+                    p0y_max: float = 0.3) -> List[Workload]:
+    """Batching workload: `count` independent instances with seeded parameters.
+
+    Per instance, in this draw order: N uniform over `sizes` (square N x N
+    grid with dx = lambda/32, so the box is N/32 wavelengths), w0 ~ U[2, 16]
+    lambda, A0 ~ U[0.05, 1.0], p0y ~ U[0, p0y_max] k_L, spin +1 or -1 with
+    probability 1/2.  Packet at p0x = -k_L, sigma_x = 3 lambda, centred on
+    the focus; dt = T_L/64; `steps` steps each.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(sizes[int(rng.integers(len(sizes)))])
+        w0 = float(rng.uniform(2.0, 16.0)) * LAMBDA_L
+        a0 = float(rng.uniform(0.05, 1.0))
+        p0y = float(rng.uniform(0.0, p0y_max)) * K_L
+        spin = 1 if rng.random() < 0.5 else -1
+        g = square_box(n, n // 32)
+        b = BeamSpec(a0=a0, w0=w0)
+        p = PacketSpec(p0y=p0y, spin=spin)
+        out.append(Workload(f"batch{i}_grid{n}_w{w0 / LAMBDA_L:.3f}_a{a0:.4f}_py{p0y / K_L:.4f}_s{spin:+d}",
+                            g, b, p, obs_for(g, p, spin0=spin), steps=steps,
+                            meta={"seed": seed, "index": i}))
+    return out
+
+
 def random_state(ny: int, nx: int, seed: int, ncomp: int = 4) -> np.ndarray:
     """Seeded complex128 test state with unit norm (not a physical packet)."""
     rng = np.random.default_rng(seed)

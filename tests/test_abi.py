@@ -99,3 +99,85 @@ def test_calls_on_null_context_fail_cleanly():
     out = (ctypes.c_double * 8)()
     assert L.qw_kernel_times(None, out, 8, None) == qw.QW_E_ARG
     L.qw_destroy(None)
+
+
+# ---- batched form: host-only checks -------------------------------------
+def inst(n=64, prec=qw.QW_F32, nx=None, ny=None, beam=None):
+    g = grid(n, prec, nx, ny)
+    b = W.BeamSpec() if beam is None else beam
+    return qw.qw_instance(g, qw._beam_struct(b))
+
+
+def test_batch_layout_offsets_are_aligned_and_packed():
+    items = [inst(256), inst(64), inst(1024), inst(128, nx=128, ny=64)]
+    offs, state_bytes, ws_bytes = qw.qw_batch_layout(items)
+    sizes = [256 * 256, 64 * 64, 1024 * 1024, 128 * 64]
+    assert offs[0] == 0
+    for i in range(len(items)):
+        assert offs[i] % 256 == 0
+        end = offs[i] + sizes[i] * 4 * 8
+        nxt = offs[i + 1] if i + 1 < len(items) else state_bytes
+        assert end <= nxt < end + 256
+    # the workspace holds at least one state-sized plane
+    assert ws_bytes >= state_bytes and ws_bytes % 256 == 0
+
+
+@pytest.mark.parametrize("prec,n,code", [(qw.QW_F32, 32, qw.QW_E_SIZE), (qw.QW_F32, 4096, qw.QW_E_SIZE),
+                                          (qw.QW_F64, 2048, qw.QW_E_SIZE), (qw.QW_F64, 48, qw.QW_E_SIZE)])
+def test_batch_rejects_sizes_outside_the_batched_range(prec, n, code):
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_batch_layout([inst(64, prec), inst(n, prec)])
+    assert e.value.code == code
+    assert "instance 1" in qw.qw_batch_last_error(None)
+
+
+def test_batch_rejects_mixed_precision_bad_beam_and_count():
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_batch_layout([inst(64, qw.QW_F32), inst(64, qw.QW_F64)])
+    assert e.value.code == qw.QW_E_ARG and "precision" in qw.qw_batch_last_error(None)
+    bad = W.BeamSpec(w0=-1.0)
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_batch_layout([inst(64), inst(64, beam=bad)])
+    assert e.value.code == qw.QW_E_ARG and "w0" in qw.qw_batch_last_error(None)
+    L = qw.lib()
+    assert L.qw_batch_layout(None, 1, None, None, None) == qw.QW_E_ARG
+    arr = (qw.qw_instance * 1)(inst(64))
+    assert L.qw_batch_layout(arr, 0, None, None, None) == qw.QW_E_ARG
+
+
+def test_batch_init_rejects_bad_workspace_on_host():
+    items = [inst(64)]
+    _, _, ws = qw.qw_batch_layout(items)
+    L = qw.lib()
+    h = ctypes.c_void_p()
+    arr = (qw.qw_instance * 1)(*items)
+    assert L.qw_batch_init(ctypes.byref(h), arr, 1, None, ws, None) == qw.QW_E_ARG
+    assert L.qw_batch_init(ctypes.byref(h), arr, 1, ctypes.c_void_p(256), ws - 1, None) == qw.QW_E_WORKSPACE
+    assert L.qw_batch_init(ctypes.byref(h), arr, 1, ctypes.c_void_p(257), ws, None) == qw.QW_E_WORKSPACE
+    assert h.value is None
+
+
+def test_batch_calls_reject_null_handle():
+    L = qw.lib()
+    vp = ctypes.c_void_p
+    assert L.qw_batch_step_n(None, vp(256), 1, 0.0, 1e-5, None) == qw.QW_E_ARG
+    assert L.qw_batch_set_launch(None, 0, 0, 0) == qw.QW_E_ARG
+    assert L.qw_batch_set_schedule(None, 6, 0, 0) == qw.QW_E_ARG
+    assert L.qw_batch_kernel_timing(None, 1) == qw.QW_E_ARG
+    L.qw_batch_destroy(None)
+
+
+def test_batch_workload_draws_are_seeded_and_in_range():
+    a = W.batch_instances(seed=0)
+    b = W.batch_instances(seed=0)
+    assert [w.name for w in a] == [w.name for w in b] and len(a) == 96
+    for w in a:
+        n = w.grid.nx
+        assert n in (256, 512, 1024) and w.grid.ny == n
+        assert abs(w.grid.lx - n * W.LAMBDA_L / 32) < 1e-12
+        assert 2 * W.LAMBDA_L <= w.beam.w0 <= 16 * W.LAMBDA_L
+        assert 0.05 <= w.beam.a0 <= 1.0
+        assert 0 <= w.packet.p0y <= 0.3 * W.K_L and w.packet.spin in (1, -1)
+        assert w.obs.spin0 == w.packet.spin and w.obs.band_half_idx == n // 32
+    assert {w.grid.nx for w in a} == {256, 512, 1024}
+    assert 30 <= sum(w.packet.spin == 1 for w in a) <= 66
