@@ -10,6 +10,8 @@ HBM.  Afterwards, untimed:
     result is compared with (max absolute error);
   * a shorter run with per-launch HIP events, giving the average duration of
     each pass and its fraction of the HBM roofline;
+  * the batching workload (96 uneven instances, autotuned): batched and
+    one-by-one rates and their ratio;
   * the oracle (FP64 CPU) on a bounded sample of the same workload.
 Prints one JSON line on stdout; progress goes to stderr.
 
@@ -84,6 +86,76 @@ def kernel_times(qw, sim, wl, steps, torch):
     return {"row": (cnt_r, ms_r), "col": (cnt_c, ms_c)}
 
 
+def batch_section(qw, W, torch, steps, single_steps):
+    """Batching workload: 96 seeded instances of 256^2 / 512^2 / 1024^2 FP32.
+
+    Autotunes the batch, times `steps` batched steps (one launch per pass over
+    all instances, graph-captured step loop), then the per-pass kernel times,
+    then the same instances advanced one by one with the single-instance call
+    for `single_steps` steps each.  Per-step work is the same in every step, so
+    the two rates compare directly.
+    """
+    wls = W.batch_instances(seed=0)
+    cells = sum(w.grid.nx * w.grid.ny for w in wls)
+    log(f"batch: {len(wls)} instances, {cells} cells; autotune")
+    bt = qw.Batch([(w.grid, w.beam) for w in wls], qw.QW_F32)
+    bt.init_packets([w.packet for w in wls])
+    rows = bt.autotune(W.DT, reps=10)
+    chosen = {"row": {}, "col": {}}
+    for kind, pass_ in ((0, "row"), (1, "col")):
+        best = {}
+        for r in rows:
+            if int(r[0]) == kind and (int(r[1]) not in best or r[3] < best[int(r[1])][1]):
+                best[int(r[1])] = (int(r[2]), r[3])
+        for lg, (v, _) in sorted(best.items()):
+            chosen[pass_][str(1 << lg)] = bt.schedule(lg, v)
+    launches = {}
+    for kind, pass_ in ((2, "row"), (3, "col")):
+        cand = [(r[3], int(r[1])) for r in rows if int(r[0]) == kind]
+        launches[pass_ + "_wg_per_cu"] = min(cand)[1] if cand else 0
+    bt.init_packets([w.packet for w in wls])
+    bt.step(20, 0.0, W.DT)
+    bt.init_packets([w.packet for w in wls])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(steps, 0.0, W.DT)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    value = cells * steps / tb
+    log(f"batch: {steps} steps in {tb:.3f} s -> {value:.4e} cell-steps/s")
+    qw.qw_batch_kernel_timing(bt.b, True)
+    bt.step(min(200, steps), 0.0, W.DT)
+    cnt_r, ms_r, cnt_c, ms_c = qw.qw_batch_kernel_times(bt.b, bt.stream())
+    qw.qw_batch_kernel_timing(bt.b, False)
+    bt.close()
+    row_us, col_us = 1e3 * ms_r / max(cnt_r, 1), 1e3 * ms_c / max(cnt_c, 1)
+    sims = []
+    for w in wls:
+        sm = qw.Sim(w.grid, qw.QW_F32, beam=w.beam)
+        sm.init_packet(w.packet)
+        sims.append(sm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sm in sims:
+        sm.step(single_steps, 0.0, W.DT)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for sm in sims:
+        sm.close()
+    single = cells * single_steps / ts
+    log(f"batch: one by one {single:.4e} cell-steps/s; speedup {value / single:.3f}")
+    return {"workload": "96 instances, N in {256, 512, 1024} (seed 0), w0 ~ U[2,16] lambda, A0 ~ U[0.05,1], "
+                        "p0y ~ U[0,0.3] k_L, spin +-1, FP32",
+            "instances": len(wls), "cells": cells, "steps": steps, "value": value, "unit": "cell-steps/s",
+            "ms_per_step": 1e3 * tb / steps, "GBps": round(128 * value / 1e9, 1),
+            "single_value": single, "single_steps": single_steps,
+            "speedup_batched_vs_single": value / single,
+            "avg_launch_us": {"row": round(row_us, 2), "col": round(col_us, 2)},
+            "pass_GBps": {"row": round(64 * cells / (row_us * 1e-6) / 1e9, 1),
+                          "col": round(64 * cells / (col_us * 1e-6) / 1e9, 1)},
+            "schedules": chosen, "launch": launches}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +164,10 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=2000)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--batch-steps", type=int, default=2000,
+                    help="steps of the batching workload (96 instances) to time; 0 skips it")
+    ap.add_argument("--batch-single-steps", type=int, default=500,
+                    help="steps per instance when the same instances run one by one")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
                          "128 MiB written), the reference for bandwidth and traffic counters")
@@ -179,6 +255,9 @@ def main():
         extra["probabilities_f64"] = {"P": o64["P"], "Pp": o64["Pp"], "Pm": o64["Pm"],
                                       "P_flip": o64["P_flip"], "P_neg": o64["P_neg"]}
         log(f"FP64: {t64:.3f} s; FP32 max |dP| = {err['max_abs_prob']:.3e}")
+
+    if a.batch_steps > 0:
+        extra["batch"] = batch_section(qw, W, torch, a.batch_steps, a.batch_single_steps)
 
     # oracle on a bounded sample: the same grid and field, a few steps
     import oracle
