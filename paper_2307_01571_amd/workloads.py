@@ -172,6 +172,39 @@ def batch_instances(seed: int = 0, count: int = 96, sizes=(256, 512, 1024), step
     return out
 
 
+# ---- learned form: the surrogate network's shape, input map and seeded start ----
+SURROGATE_SHAPE = dict(n_in=5, width=256, depth=4, n_out=6, n_nets=4)
+# inputs (w0, A0, interaction time, p0y, spin) are mapped to about [-1, 1]
+# by (x - shift) * scale over the ranges the batching workload draws from
+SURROGATE_INPUT_RANGES = ((2.0 * LAMBDA_L, 16.0 * LAMBDA_L), (0.05, 1.0), (0.0, 20_000 * DT),
+                          (0.0, 0.3 * K_L), (-1.0, 1.0))
+SURROGATE_OUTPUTS = ("P_0", "P_+1", "P_-1", "P_+2", "P_-2", "P_flip")
+
+
+def surrogate_input_map():
+    """(shift, scale) of the surrogate's input normalisation."""
+    shift = np.array([(lo + hi) / 2 for lo, hi in SURROGATE_INPUT_RANGES])
+    scale = np.array([2.0 / (hi - lo) for lo, hi in SURROGATE_INPUT_RANGES])
+    return shift, scale
+
+
+def mlp_layer_sizes(n_in: int, width: int, depth: int, n_out: int):
+    """(out, in) of every linear layer of an MLP with `depth` hidden layers."""
+    return [(width, n_in)] + [(width, width)] * (depth - 1) + [(n_out, width)]
+
+
+def mlp_init_params(seed: int, n_in: int, width: int, depth: int, n_out: int) -> np.ndarray:
+    """Seeded initial parameters, flat: per layer W[out][in] row-major then b[out];
+    W ~ U(-1/sqrt(in), 1/sqrt(in)), b = 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for no, ni in mlp_layer_sizes(n_in, width, depth, n_out):
+        lim = 1.0 / math.sqrt(ni)
+        parts.append(rng.uniform(-lim, lim, size=no * ni))
+        parts.append(np.zeros(no))
+    return np.concatenate(parts)
+
+
 def random_state(ny: int, nx: int, seed: int, ncomp: int = 4) -> np.ndarray:
     """Seeded complex128 test state with unit norm (not a physical packet)."""
     rng = np.random.default_rng(seed)
