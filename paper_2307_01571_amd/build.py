@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 # the slowest translation units first
 SOURCES = ["qw_batch_f32.hip", "qw_kernels_f32.hip", "qw_batch_f64.hip", "qw_kernels_f64.hip", "qw_common.hip",
-           "qw_api.cpp", "qw_batch.cpp"]
+           "qw_mlp_kernels.hip", "qw_api.cpp", "qw_batch.cpp", "qw_mlp.cpp"]
 # per-file flags: the batched kernels are built without machine loop-invariant
 # code motion (see qw_batch_f32.hip)
 SOURCE_FLAGS = {

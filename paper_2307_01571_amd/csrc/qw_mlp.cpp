@@ -1,0 +1,567 @@
+// qw_mlp.cpp -- host engine of the surrogate network (qw_mlp_* in qw_mlp.h):
+// workspace carving and the launch sequences of the forward pass, the
+// back-propagation and the Adam step.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qw.h"
+#include "qw_mlp.h"
+#include "qw_mlp_launch.hpp"
+
+namespace {
+
+using qwm::kInPad;
+
+constexpr size_t kAlign = 256;
+constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+int round64(int v) { return (v + 63) / 64 * 64; }
+
+struct Layer {
+    int n_out, n_in, in_pad, out_pad;
+    long long p_off, b_off;  // weights and bias in the flat parameters of one net
+    long long wb_off, wt_off;
+};
+
+struct Plan {
+    qw_mlp_shape s{};
+    int L = 0;             // linear layers = depth + 1
+    long long np = 0;      // parameters per net
+    long long nwb = 0;     // bfloat16 weight elements per net (each layout)
+    int Mpad = 0;          // batch rows, padded
+    std::vector<Layer> layer;
+    // byte offsets
+    size_t P, Mo, V, G, Wb, Wt, shift, scale, Xb, Xt, Z, H, Ht, Y, dYb, dYt, dZb, dZt, loss_part, loss;
+    size_t total;
+};
+
+int check_shape(const qw_mlp_shape* s, std::string* msg)
+{
+    if (!s) {
+        *msg = "shape is NULL";
+        return QW_E_ARG;
+    }
+    if (s->n_in < 1 || s->n_in > kInPad || s->n_out < 1 || s->n_out > kInPad || s->depth < 1 || s->depth > 16 ||
+        s->n_nets < 1 || s->n_nets > 16 || s->max_batch < 1 || s->max_batch > 65536 || s->width < 64 ||
+        s->width > 1024 || s->width % 64 != 0) {
+        char buf[256];
+        snprintf(buf, sizeof buf,
+                 "shape n_in=%d width=%d depth=%d n_out=%d n_nets=%d max_batch=%d outside the supported range",
+                 s->n_in, s->width, s->depth, s->n_out, s->n_nets, s->max_batch);
+        *msg = buf;
+        return QW_E_SIZE;
+    }
+    return QW_OK;
+}
+
+Plan make_plan(const qw_mlp_shape& s)
+{
+    Plan p;
+    p.s = s;
+    p.L = s.depth + 1;
+    p.Mpad = round64(s.max_batch);
+    long long o = 0, w = 0;
+    for (int l = 0; l < p.L; ++l) {
+        Layer y;
+        y.n_in = l == 0 ? s.n_in : s.width;
+        y.n_out = l == p.L - 1 ? s.n_out : s.width;
+        y.in_pad = l == 0 ? kInPad : s.width;
+        y.out_pad = l == p.L - 1 ? kInPad : s.width;
+        y.p_off = o;
+        o += (long long)y.n_out * y.n_in;
+        y.b_off = o;
+        o += y.n_out;
+        y.wb_off = w;
+        y.wt_off = w;
+        w += (long long)y.out_pad * y.in_pad;
+        p.layer.push_back(y);
+    }
+    p.np = o;
+    p.nwb = w;
+    const long long nets = s.n_nets, M = p.Mpad, W = s.width, D = s.depth;
+    size_t b = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = b;
+        b = align_up(b + bytes);
+        return at;
+    };
+    p.P = take(4 * nets * p.np);
+    p.Mo = take(4 * nets * p.np);
+    p.V = take(4 * nets * p.np);
+    p.G = take(4 * nets * p.np);
+    p.Wb = take(2 * nets * p.nwb);
+    p.Wt = take(2 * nets * p.nwb);
+    p.shift = take(4 * kInPad);
+    p.scale = take(4 * kInPad);
+    p.Xb = take(2 * M * kInPad);
+    p.Xt = take(2 * M * kInPad);
+    p.Z = take(4 * nets * D * M * W);
+    p.H = take(2 * nets * D * M * W);
+    p.Ht = take(2 * nets * D * M * W);
+    p.Y = take(4 * nets * M * kInPad);
+    p.dYb = take(2 * nets * M * kInPad);
+    p.dYt = take(2 * nets * M * kInPad);
+    p.dZb = take(2 * nets * 2 * M * W);
+    p.dZt = take(2 * nets * 2 * M * W);
+    p.loss_part = take(4 * nets * (M / 64));
+    p.loss = take(4 * nets);
+    p.total = b;
+    return p;
+}
+
+}  // namespace
+
+struct qw_mlp_s {
+    Plan p;
+    char* ws = nullptr;
+    long long t = 0;  // Adam steps taken
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_mlp_error;
+
+int mfail(qw_mlp h, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_mlp_error = buf;
+    return code;
+}
+
+int mhip(qw_mlp h, hipError_t e, const char* what) { return mfail(h, QW_E_DEVICE, "%s: %s", what, hipGetErrorString(e)); }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <typename T>
+T* at(qw_mlp h, size_t off)
+{
+    return reinterpret_cast<T*>(h->ws + off);
+}
+
+qwm::AdamArgs adam_args(qw_mlp h, int update, float lr)
+{
+    const Plan& p = h->p;
+    qwm::AdamArgs a{};
+    a.p = at<float>(h, p.P);
+    a.m = at<float>(h, p.Mo);
+    a.v = at<float>(h, p.V);
+    a.g = at<float>(h, p.G);
+    a.n = (int)p.np;
+    a.update = update;
+    a.lr = lr;
+    a.b1 = kB1;
+    a.b2 = kB2;
+    a.eps = kEps;
+    if (update) {
+        a.c1 = (float)(1.0 / (1.0 - std::pow((double)kB1, (double)h->t)));
+        a.c2 = (float)(1.0 / (1.0 - std::pow((double)kB2, (double)h->t)));
+    }
+    a.wb = at<__bf16>(h, p.Wb);
+    a.wt = at<__bf16>(h, p.Wt);
+    a.s_wb = p.nwb;
+    a.s_wt = p.nwb;
+    a.n_layers = p.L;
+    for (int l = 0; l < p.L; ++l) {
+        const Layer& y = p.layer[l];
+        a.layer[l] = qwm::LayerMap{(int)y.p_off, y.n_out, y.n_in, (int)y.wb_off, y.in_pad, (int)y.wt_off, y.out_pad};
+    }
+    return a;
+}
+
+// Forward pass of every net for B samples.  With t (targets) the training
+// outputs are kept: pre-activations, transposed activations, dY and the loss
+// partials.
+hipError_t forward(qw_mlp h, const float* x, const float* t, int B, hipStream_t s)
+{
+    const Plan& p = h->p;
+    const int W = p.s.width, D = p.s.depth, M = p.Mpad, nets = p.s.n_nets;
+    const int Mp = round64(B);
+    const bool train = t != nullptr;
+    hipError_t e = qwm::launch_prep_input(x, B, p.s.n_in, Mp, at<float>(h, p.shift), at<float>(h, p.scale),
+                                          at<__bf16>(h, p.Xb), at<__bf16>(h, p.Xt), s);
+    // note: Xt rows are Mp long here (ld = Mp); the products below read them with ld = Mp
+    const long long sAct = (long long)D * M * W;  // per-net stride of Z, H, Ht
+    for (int l = 0; l < D && e == hipSuccess; ++l) {
+        const Layer& y = p.layer[l];
+        qwm::GemmArgs g{};
+        if (l == 0) {
+            g.A = at<__bf16>(h, p.Xb);
+            g.sA = 0;
+            g.lda = kInPad;
+        } else {
+            g.A = at<__bf16>(h, p.H) + (size_t)(l - 1) * M * W;
+            g.sA = sAct;
+            g.lda = W;
+        }
+        g.B = at<__bf16>(h, p.Wb) + y.wb_off;
+        g.sB = p.nwb;
+        g.ldb = y.in_pad;
+        g.M = B;
+        g.N = W;
+        g.K = y.in_pad;
+        g.Mpad = Mp;
+        g.bias = at<float>(h, p.P) + y.b_off;
+        g.sbias = p.np;
+        if (train) {
+            g.Cf = at<float>(h, p.Z) + (size_t)l * M * W;
+            g.sCf = sAct;
+            g.ldcf = W;
+            g.Ct = at<__bf16>(h, p.Ht) + (size_t)l * M * W;
+            g.sCt = sAct;
+            g.ldct = Mp;
+            g.nct = W;
+        }
+        g.Cb = at<__bf16>(h, p.H) + (size_t)l * M * W;
+        g.sCb = sAct;
+        g.ldcb = W;
+        e = qwm::launch_gemm(qwm::EPI_HIDDEN, g, nets, W, s);
+    }
+    if (e != hipSuccess) return e;
+    const Layer& y = p.layer[D];
+    qwm::GemmArgs g{};
+    g.A = at<__bf16>(h, p.H) + (size_t)(D - 1) * M * W;
+    g.sA = sAct;
+    g.lda = W;
+    g.B = at<__bf16>(h, p.Wb) + y.wb_off;
+    g.sB = p.nwb;
+    g.ldb = W;
+    g.M = B;
+    g.N = p.s.n_out;
+    g.K = W;
+    g.Mpad = Mp;
+    g.bias = at<float>(h, p.P) + y.b_off;
+    g.sbias = p.np;
+    g.Cf = at<float>(h, p.Y);
+    g.sCf = (long long)M * kInPad;
+    g.ldcf = kInPad;
+    if (train) {
+        g.T = t;
+        g.ldt = p.s.n_out;
+        g.gscale = 2.0f / ((float)B * (float)p.s.n_out);
+        g.Cb = at<__bf16>(h, p.dYb);
+        g.sCb = (long long)M * kInPad;
+        g.ldcb = kInPad;
+        g.Ct = at<__bf16>(h, p.dYt);
+        g.sCt = (long long)M * kInPad;
+        g.ldct = Mp;
+        g.nct = kInPad;
+        g.loss_part = at<float>(h, p.loss_part);
+        g.sLoss = M / 64;
+    }
+    e = qwm::launch_gemm(qwm::EPI_OUT, g, nets, kInPad, s);
+    if (e == hipSuccess && train)
+        e = qwm::launch_loss_finish(at<float>(h, p.loss_part), M / 64, Mp / 64, 1.0f / ((float)B * p.s.n_out),
+                                    at<float>(h, p.loss), nets, s);
+    return e;
+}
+
+// weight gradient dW[out][in] = sum_m dZt[out][m] Ht[in][m] (+ bias gradient as row sums of dZt)
+hipError_t weight_grad(qw_mlp h, int l, const __bf16* dzt, long long s_dzt, const __bf16* ht, long long s_ht,
+                       int Mp, int B, hipStream_t s)
+{
+    const Plan& p = h->p;
+    const Layer& y = p.layer[l];
+    qwm::GemmArgs g{};
+    g.A = dzt;
+    g.sA = s_dzt;
+    g.lda = Mp;
+    g.B = ht;
+    g.sB = s_ht;
+    g.ldb = Mp;
+    g.M = y.n_out;
+    g.N = y.n_in;
+    g.K = Mp;
+    g.Mpad = round64(y.n_out);
+    g.Cf = at<float>(h, p.G) + y.p_off;
+    g.sCf = p.np;
+    g.ldcf = y.n_in;
+    hipError_t e = qwm::launch_gemm(qwm::EPI_F32, g, p.s.n_nets, y.n_in, s);
+    if (e == hipSuccess)
+        e = qwm::launch_row_sums(dzt, s_dzt, Mp, y.n_out, B, at<float>(h, p.G) + y.b_off, p.np, p.s.n_nets, s);
+    return e;
+}
+
+// dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1}) from dZ_l [B][kpad] (row-major) and Wt_l
+hipError_t act_grad(qw_mlp h, int l, const __bf16* dzb, long long s_dzb, int lda, __bf16* out_b, __bf16* out_t,
+                    long long s_out, int Mp, int B, hipStream_t s)
+{
+    const Plan& p = h->p;
+    const Layer& y = p.layer[l];
+    const int W = p.s.width, M = p.Mpad;
+    qwm::GemmArgs g{};
+    g.A = dzb;
+    g.sA = s_dzb;
+    g.lda = lda;
+    g.B = at<__bf16>(h, p.Wt) + y.wt_off;
+    g.sB = p.nwb;
+    g.ldb = y.out_pad;
+    g.M = B;
+    g.N = W;
+    g.K = y.out_pad;
+    g.Mpad = Mp;
+    g.Z = at<float>(h, p.Z) + (size_t)(l - 1) * M * W;
+    g.sZ = (long long)p.s.depth * M * W;
+    g.ldz = W;
+    g.Cb = out_b;
+    g.sCb = s_out;
+    g.ldcb = W;
+    g.Ct = out_t;
+    g.sCt = s_out;
+    g.ldct = Mp;
+    g.nct = W;
+    return qwm::launch_gemm(qwm::EPI_GELU_BWD, g, p.s.n_nets, W, s);
+}
+
+hipError_t backward(qw_mlp h, int B, hipStream_t s)
+{
+    const Plan& p = h->p;
+    const int W = p.s.width, D = p.s.depth, M = p.Mpad;
+    const int Mp = round64(B);
+    const long long sAct = (long long)D * M * W;
+    const long long sY = (long long)M * kInPad;
+    const long long sdz = 2LL * M * W;
+    // output layer
+    hipError_t e = weight_grad(h, D, at<__bf16>(h, p.dYt), sY, at<__bf16>(h, p.Ht) + (size_t)(D - 1) * M * W, sAct,
+                               Mp, B, s);
+    int cur = 0;
+    if (e == hipSuccess)
+        e = act_grad(h, D, at<__bf16>(h, p.dYb), sY, kInPad, at<__bf16>(h, p.dZb), at<__bf16>(h, p.dZt), sdz, Mp, B, s);
+    for (int l = D - 1; l >= 1 && e == hipSuccess; --l) {
+        const __bf16* dzt = at<__bf16>(h, p.dZt) + (size_t)cur * M * W;
+        const __bf16* dzb = at<__bf16>(h, p.dZb) + (size_t)cur * M * W;
+        e = weight_grad(h, l, dzt, sdz, at<__bf16>(h, p.Ht) + (size_t)(l - 1) * M * W, sAct, Mp, B, s);
+        const int nxt = 1 - cur;
+        if (e == hipSuccess)
+            e = act_grad(h, l, dzb, sdz, W, at<__bf16>(h, p.dZb) + (size_t)nxt * M * W,
+                         at<__bf16>(h, p.dZt) + (size_t)nxt * M * W, sdz, Mp, B, s);
+        cur = nxt;
+    }
+    if (e == hipSuccess)
+        e = weight_grad(h, 0, at<__bf16>(h, p.dZt) + (size_t)cur * M * W, sdz, at<__bf16>(h, p.Xt), 0, Mp, B, s);
+    return e;
+}
+
+int check_batch(qw_mlp h, const float* x, int B)
+{
+    if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
+    if (!x) return mfail(h, QW_E_ARG, "x is NULL");
+    if (B < 1 || B > h->p.s.max_batch) return mfail(h, QW_E_ARG, "batch %d outside [1, %d]", B, h->p.s.max_batch);
+    return QW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qw_mlp_param_count(const qw_mlp_shape* s, int64_t* per_net)
+{
+    std::string msg;
+    const int rc = check_shape(s, &msg);
+    if (rc != QW_OK) return mfail(nullptr, rc, "%s", msg.c_str());
+    if (!per_net) return mfail(nullptr, QW_E_ARG, "per_net is NULL");
+    *per_net = make_plan(*s).np;
+    return QW_OK;
+}
+
+int qw_mlp_workspace_bytes(const qw_mlp_shape* s, size_t* bytes)
+{
+    std::string msg;
+    const int rc = check_shape(s, &msg);
+    if (rc != QW_OK) return mfail(nullptr, rc, "%s", msg.c_str());
+    if (!bytes) return mfail(nullptr, QW_E_ARG, "bytes is NULL");
+    *bytes = make_plan(*s).total;
+    return QW_OK;
+}
+
+int qw_mlp_init(qw_mlp* out, const qw_mlp_shape* s, const float* shift, const float* scale, void* workspace,
+                size_t ws_bytes, void* hip_stream)
+{
+    if (!out) return mfail(nullptr, QW_E_ARG, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    int rc = check_shape(s, &msg);
+    if (rc != QW_OK) return mfail(nullptr, rc, "%s", msg.c_str());
+    if (!shift || !scale) return mfail(nullptr, QW_E_ARG, "shift or scale is NULL");
+    for (int i = 0; i < s->n_in; ++i)
+        if (!std::isfinite(shift[i]) || !std::isfinite(scale[i]))
+            return mfail(nullptr, QW_E_ARG, "input map entry %d is not finite", i);
+    if (!workspace) return mfail(nullptr, QW_E_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return mfail(nullptr, QW_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    Plan p = make_plan(*s);
+    if (ws_bytes < p.total)
+        return mfail(nullptr, QW_E_WORKSPACE, "workspace has %zu bytes, the network needs %zu", ws_bytes, p.total);
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return mfail(nullptr, QW_E_ARG, "workspace is not device memory");
+    }
+    qw_mlp h = new (std::nothrow) qw_mlp_s;
+    if (!h) return mfail(nullptr, QW_E_DEVICE, "out of host memory");
+    h->p = p;
+    h->ws = static_cast<char*>(workspace);
+    hipStream_t st = as_stream(hip_stream);
+    float map[2 * kInPad] = {};
+    for (int i = 0; i < s->n_in; ++i) {
+        map[i] = shift[i];
+        map[kInPad + i] = scale[i];
+    }
+    // zero everything (the paddings of weights and activations must read as zero)
+    hipError_t e = qwm::launch_fill_zero(h->ws, p.total, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(at<float>(h, p.shift), map, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<float>(h, p.scale), map + kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        mfail(nullptr, QW_E_DEVICE, "network set-up: %s", hipGetErrorString(e));
+        delete h;
+        return QW_E_DEVICE;
+    }
+    *out = h;
+    return QW_OK;
+}
+
+int qw_mlp_set_params(qw_mlp h, const float* params, void* hip_stream)
+{
+    if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
+    if (!params) return mfail(h, QW_E_ARG, "params is NULL");
+    const Plan& p = h->p;
+    hipStream_t s = as_stream(hip_stream);
+    const size_t bytes = 4 * (size_t)p.s.n_nets * p.np;
+    hipError_t e = hipMemcpyAsync(at<float>(h, p.P), params, bytes, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = qwm::launch_fill_zero(at<float>(h, p.Mo), bytes, s);
+    if (e == hipSuccess) e = qwm::launch_fill_zero(at<float>(h, p.V), bytes, s);
+    if (e == hipSuccess) e = qwm::launch_adam(adam_args(h, 0, 0.0f), p.s.n_nets, s);
+    if (e != hipSuccess) return mhip(h, e, "set params");
+    h->t = 0;
+    return QW_OK;
+}
+
+int qw_mlp_get_params(qw_mlp h, float* params, void* hip_stream)
+{
+    if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
+    if (!params) return mfail(h, QW_E_ARG, "params is NULL");
+    const hipError_t e = hipMemcpyAsync(params, at<float>(h, h->p.P), 4 * (size_t)h->p.s.n_nets * h->p.np,
+                                        hipMemcpyDeviceToDevice, as_stream(hip_stream));
+    if (e != hipSuccess) return mhip(h, e, "get params");
+    return QW_OK;
+}
+
+int qw_mlp_forward(qw_mlp h, const float* x, int32_t B, float* y, void* hip_stream)
+{
+    int rc = check_batch(h, x, B);
+    if (rc != QW_OK) return rc;
+    if (!y) return mfail(h, QW_E_ARG, "y is NULL");
+    hipStream_t s = as_stream(hip_stream);
+    const Plan& p = h->p;
+    hipError_t e = forward(h, x, nullptr, B, s);
+    // compact [net][B][n_out] from the padded [net][Mpad][16]
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(y, sizeof(float) * p.s.n_out, at<float>(h, p.Y), sizeof(float) * kInPad,
+                             sizeof(float) * p.s.n_out, (size_t)B, hipMemcpyDeviceToDevice, s);
+    for (int k = 1; k < p.s.n_nets && e == hipSuccess; ++k)
+        e = hipMemcpy2DAsync(y + (size_t)k * B * p.s.n_out, sizeof(float) * p.s.n_out,
+                             at<float>(h, p.Y) + (size_t)k * p.Mpad * kInPad, sizeof(float) * kInPad,
+                             sizeof(float) * p.s.n_out, (size_t)B, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mhip(h, e, "forward");
+    return QW_OK;
+}
+
+int qw_mlp_predict(qw_mlp h, const float* x, int32_t B, float* mean, float* spread, void* hip_stream)
+{
+    int rc = check_batch(h, x, B);
+    if (rc != QW_OK) return rc;
+    if (!mean || !spread) return mfail(h, QW_E_ARG, "mean or spread is NULL");
+    hipStream_t s = as_stream(hip_stream);
+    const Plan& p = h->p;
+    hipError_t e = forward(h, x, nullptr, B, s);
+    if (e == hipSuccess)
+        e = qwm::launch_ensemble(at<float>(h, p.Y), (long long)p.Mpad * kInPad, kInPad, B, p.s.n_out, p.s.n_nets,
+                                 mean, spread, s);
+    if (e != hipSuccess) return mhip(h, e, "predict");
+    return QW_OK;
+}
+
+int qw_mlp_gradients(qw_mlp h, const float* x, const float* t, int32_t B, float* grads, float* loss,
+                     void* hip_stream)
+{
+    int rc = check_batch(h, x, B);
+    if (rc != QW_OK) return rc;
+    if (!t) return mfail(h, QW_E_ARG, "t is NULL");
+    hipStream_t s = as_stream(hip_stream);
+    const Plan& p = h->p;
+    hipError_t e = forward(h, x, t, B, s);
+    if (e == hipSuccess) e = backward(h, B, s);
+    if (e == hipSuccess && grads)
+        e = hipMemcpyAsync(grads, at<float>(h, p.G), 4 * (size_t)p.s.n_nets * p.np, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && loss)
+        e = hipMemcpyAsync(loss, at<float>(h, p.loss), 4 * (size_t)p.s.n_nets, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mhip(h, e, "gradients");
+    return QW_OK;
+}
+
+int qw_mlp_train_step(qw_mlp h, const float* x, const float* t, int32_t B, float lr, float* loss, void* hip_stream)
+{
+    int rc = check_batch(h, x, B);
+    if (rc != QW_OK) return rc;
+    if (!t) return mfail(h, QW_E_ARG, "t is NULL");
+    if (!std::isfinite(lr) || lr < 0) return mfail(h, QW_E_ARG, "learning rate must be finite and >= 0");
+    hipStream_t s = as_stream(hip_stream);
+    const Plan& p = h->p;
+    hipError_t e = forward(h, x, t, B, s);
+    if (e == hipSuccess) e = backward(h, B, s);
+    h->t += 1;
+    if (e == hipSuccess) e = qwm::launch_adam(adam_args(h, 1, lr), p.s.n_nets, s);
+    if (e == hipSuccess && loss)
+        e = hipMemcpyAsync(loss, at<float>(h, p.loss), 4 * (size_t)p.s.n_nets, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mhip(h, e, "train step");
+    return QW_OK;
+}
+
+int qw_gemm_bf16_nt(const void* A, int32_t lda, const void* B, int32_t ldb, float* C, int32_t ldc, int32_t M,
+                    int32_t N, int32_t K, void* hip_stream)
+{
+    if (!A || !B || !C) return mfail(nullptr, QW_E_ARG, "A, B or C is NULL");
+    if (M < 1 || N < 1 || K < 16 || K % 16 != 0) return mfail(nullptr, QW_E_SIZE, "need M, N >= 1 and K a multiple of 16");
+    if (lda < K || ldb < K || lda % 8 != 0 || ldb % 8 != 0 || ldc < N)
+        return mfail(nullptr, QW_E_ARG, "leading dimensions: lda, ldb >= K and multiples of 8, ldc >= N");
+    if (reinterpret_cast<uintptr_t>(A) % 16 != 0 || reinterpret_cast<uintptr_t>(B) % 16 != 0)
+        return mfail(nullptr, QW_E_ARG, "A and B must be 16-byte aligned");
+    qwm::GemmArgs g{};
+    g.A = static_cast<const __bf16*>(A);
+    g.lda = lda;
+    g.B = static_cast<const __bf16*>(B);
+    g.ldb = ldb;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.Mpad = round64(M);
+    g.Cf = C;
+    g.ldcf = ldc;
+    const hipError_t e = qwm::launch_gemm(qwm::EPI_F32, g, 1, N, as_stream(hip_stream));
+    if (e != hipSuccess) return mfail(nullptr, QW_E_DEVICE, "gemm: %s", hipGetErrorString(e));
+    return QW_OK;
+}
+
+const char* qw_mlp_last_error(qw_mlp h)
+{
+    if (!h) return g_mlp_error.c_str();
+    return h->err.c_str();
+}
+
+void qw_mlp_destroy(qw_mlp h) { delete h; }
+
+}  // extern "C"

@@ -37,8 +37,12 @@ EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_init_packet
             "qw_batch_layout", "qw_batch_init", "qw_batch_init_packets", "qw_batch_step_n",
             "qw_batch_observables", "qw_batch_schedule", "qw_batch_set_schedule", "qw_batch_set_launch",
             "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
-            "qw_batch_destroy")
-_NO_STATUS = ("qw_last_error", "qw_destroy", "qw_batch_last_error", "qw_batch_destroy")
+            "qw_batch_destroy",
+            "qw_mlp_param_count", "qw_mlp_workspace_bytes", "qw_mlp_init", "qw_mlp_set_params",
+            "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_gradients", "qw_mlp_train_step",
+            "qw_gemm_bf16_nt", "qw_mlp_last_error", "qw_mlp_destroy")
+_NO_STATUS = ("qw_last_error", "qw_destroy", "qw_batch_last_error", "qw_batch_destroy", "qw_mlp_last_error",
+              "qw_mlp_destroy")
 
 
 class qw_grid(ctypes.Structure):
@@ -66,6 +70,11 @@ class qw_obs_spec(ctypes.Structure):
 
 class qw_instance(ctypes.Structure):
     _fields_ = [("grid", qw_grid), ("beam", qw_beam)]
+
+
+class qw_mlp_shape(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("width", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("n_nets", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
 
 _lib = None
@@ -111,6 +120,23 @@ def lib():
     L.qw_batch_last_error.restype = ctypes.c_char_p
     L.qw_batch_destroy.argtypes = [vp]
     L.qw_batch_destroy.restype = None
+    shp = ctypes.POINTER(qw_mlp_shape)
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.qw_mlp_param_count.argtypes = [shp, ctypes.POINTER(ctypes.c_int64)]
+    L.qw_mlp_workspace_bytes.argtypes = [shp, szp]
+    L.qw_mlp_init.argtypes = [ctypes.POINTER(vp), shp, fp, fp, vp, ctypes.c_size_t, vp]
+    L.qw_mlp_set_params.argtypes = [vp, vp, vp]
+    L.qw_mlp_get_params.argtypes = [vp, vp, vp]
+    L.qw_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+    L.qw_mlp_predict.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+    L.qw_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp]
+    L.qw_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp]
+    L.qw_gemm_bf16_nt.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_int32, vp]
+    L.qw_mlp_last_error.argtypes = [vp]
+    L.qw_mlp_last_error.restype = ctypes.c_char_p
+    L.qw_mlp_destroy.argtypes = [vp]
+    L.qw_mlp_destroy.restype = None
     for name in EXPORTED:
         if name not in _NO_STATUS:
             getattr(L, name).restype = ctypes.c_int
@@ -288,6 +314,74 @@ def qw_batch_destroy(b: int) -> None:
     lib().qw_batch_destroy(ctypes.c_void_p(b))
 
 
+# ---- surrogate network -------------------------------------------------------
+def _mcheck(rc: int, h=None):
+    if rc != QW_OK:
+        raise QWError(rc, qw_mlp_last_error(h))
+
+
+def _p(x) -> ctypes.c_void_p:
+    return ctypes.c_void_p(x)
+
+
+def qw_mlp_param_count(shape: qw_mlp_shape) -> int:
+    n = ctypes.c_int64()
+    _mcheck(lib().qw_mlp_param_count(ctypes.byref(shape), ctypes.byref(n)))
+    return n.value
+
+
+def qw_mlp_workspace_bytes(shape: qw_mlp_shape) -> int:
+    n = ctypes.c_size_t()
+    _mcheck(lib().qw_mlp_workspace_bytes(ctypes.byref(shape), ctypes.byref(n)))
+    return n.value
+
+
+def qw_mlp_init(shape: qw_mlp_shape, shift, scale, workspace_ptr: int, ws_bytes: int, stream: int) -> int:
+    h = ctypes.c_void_p()
+    sh = (ctypes.c_float * shape.n_in)(*[float(v) for v in shift])
+    sc = (ctypes.c_float * shape.n_in)(*[float(v) for v in scale])
+    _mcheck(lib().qw_mlp_init(ctypes.byref(h), ctypes.byref(shape), sh, sc, _p(workspace_ptr), ws_bytes, _p(stream)))
+    return h.value
+
+
+def qw_mlp_set_params(h: int, params_ptr: int, stream: int) -> None:
+    _mcheck(lib().qw_mlp_set_params(_p(h), _p(params_ptr), _p(stream)), h)
+
+
+def qw_mlp_get_params(h: int, params_ptr: int, stream: int) -> None:
+    _mcheck(lib().qw_mlp_get_params(_p(h), _p(params_ptr), _p(stream)), h)
+
+
+def qw_mlp_forward(h: int, x_ptr: int, B: int, y_ptr: int, stream: int) -> None:
+    _mcheck(lib().qw_mlp_forward(_p(h), _p(x_ptr), int(B), _p(y_ptr), _p(stream)), h)
+
+
+def qw_mlp_predict(h: int, x_ptr: int, B: int, mean_ptr: int, spread_ptr: int, stream: int) -> None:
+    _mcheck(lib().qw_mlp_predict(_p(h), _p(x_ptr), int(B), _p(mean_ptr), _p(spread_ptr), _p(stream)), h)
+
+
+def qw_mlp_gradients(h: int, x_ptr: int, t_ptr: int, B: int, grads_ptr, loss_ptr, stream: int) -> None:
+    _mcheck(lib().qw_mlp_gradients(_p(h), _p(x_ptr), _p(t_ptr), int(B), _p(grads_ptr), _p(loss_ptr), _p(stream)), h)
+
+
+def qw_mlp_train_step(h: int, x_ptr: int, t_ptr: int, B: int, lr: float, loss_ptr, stream: int) -> None:
+    _mcheck(lib().qw_mlp_train_step(_p(h), _p(x_ptr), _p(t_ptr), int(B), float(lr), _p(loss_ptr), _p(stream)), h)
+
+
+def qw_gemm_bf16_nt(a_ptr: int, lda: int, b_ptr: int, ldb: int, c_ptr: int, ldc: int, M: int, N: int, K: int,
+                    stream: int) -> None:
+    _mcheck(lib().qw_gemm_bf16_nt(_p(a_ptr), lda, _p(b_ptr), ldb, _p(c_ptr), ldc, M, N, K, _p(stream)))
+
+
+def qw_mlp_last_error(h=None) -> str:
+    s = lib().qw_mlp_last_error(_p(h) if h else None)
+    return s.decode() if s else ""
+
+
+def qw_mlp_destroy(h: int) -> None:
+    lib().qw_mlp_destroy(_p(h))
+
+
 # ---- convenience owner of device tensors ---------------------------------
 def unpack_observables(out, n_max: int) -> dict:
     nb = 2 * n_max + 1
@@ -438,6 +532,83 @@ class Batch:
         if self.b:
             qw_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Surrogate network ensemble on one device: workspace and parameter tensors
+    plus the handle.  x, t, outputs are torch tensors on the same device."""
+
+    def __init__(self, n_in=5, width=256, depth=4, n_out=6, n_nets=4, max_batch=4096, shift=None, scale=None,
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.shape = qw_mlp_shape(n_in, width, depth, n_out, n_nets, max_batch)
+        self.per_net = qw_mlp_param_count(self.shape)
+        nbytes = qw_mlp_workspace_bytes(self.shape)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        shift = [0.0] * n_in if shift is None else list(shift)
+        scale = [1.0] * n_in if scale is None else list(scale)
+        self.h = qw_mlp_init(self.shape, shift, scale, self.ws.data_ptr(), nbytes, self.stream())
+
+    def stream(self) -> int:
+        with self.torch.cuda.device(self.device):
+            return self.torch.cuda.current_stream().cuda_stream
+
+    def _f32(self, a):
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device)
+        return t.contiguous()
+
+    def set_params(self, flat) -> None:
+        """flat: n_nets x per_net values (host or device)."""
+        p = self._f32(flat).reshape(-1)
+        assert p.numel() == self.shape.n_nets * self.per_net
+        qw_mlp_set_params(self.h, p.data_ptr(), self.stream())
+        self.torch.cuda.synchronize(self.device)
+
+    def params(self):
+        out = self.torch.empty(self.shape.n_nets * self.per_net, dtype=self.torch.float32, device=self.device)
+        qw_mlp_get_params(self.h, out.data_ptr(), self.stream())
+        return out.view(self.shape.n_nets, self.per_net)
+
+    def forward(self, x):
+        x = self._f32(x)
+        B = x.shape[0]
+        y = self.torch.empty((self.shape.n_nets, B, self.shape.n_out), dtype=self.torch.float32, device=self.device)
+        qw_mlp_forward(self.h, x.data_ptr(), B, y.data_ptr(), self.stream())
+        return y
+
+    def predict(self, x):
+        x = self._f32(x)
+        B = x.shape[0]
+        mean = self.torch.empty((B, self.shape.n_out), dtype=self.torch.float32, device=self.device)
+        spread = self.torch.empty(B, dtype=self.torch.float32, device=self.device)
+        qw_mlp_predict(self.h, x.data_ptr(), B, mean.data_ptr(), spread.data_ptr(), self.stream())
+        return mean, spread
+
+    def gradients(self, x, t):
+        x, t = self._f32(x), self._f32(t)
+        g = self.torch.empty((self.shape.n_nets, self.per_net), dtype=self.torch.float32, device=self.device)
+        loss = self.torch.empty(self.shape.n_nets, dtype=self.torch.float32, device=self.device)
+        qw_mlp_gradients(self.h, x.data_ptr(), t.data_ptr(), x.shape[0], g.data_ptr(), loss.data_ptr(),
+                         self.stream())
+        return g, loss
+
+    def train_step(self, x, t, lr: float, loss=None):
+        """x, t: device float32 tensors (contiguous); loss: optional [n_nets] device tensor."""
+        qw_mlp_train_step(self.h, x.data_ptr(), t.data_ptr(), x.shape[0], lr,
+                          None if loss is None else loss.data_ptr(), self.stream())
+
+    def close(self) -> None:
+        if self.h:
+            qw_mlp_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -11,13 +11,17 @@ from paper_2307_01571_amd import qw
 from paper_2307_01571_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "qw.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(qw_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(qw_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -181,3 +185,28 @@ def test_batch_workload_draws_are_seeded_and_in_range():
         assert w.obs.spin0 == w.packet.spin and w.obs.band_half_idx == n // 32
     assert {w.grid.nx for w in a} == {256, 512, 1024}
     assert 30 <= sum(w.packet.spin == 1 for w in a) <= 66
+
+
+# ---- surrogate network: host-only checks ---------------------------------
+def test_mlp_param_count_matches_the_layer_sizes():
+    s = qw.qw_mlp_shape(5, 256, 4, 6, 4, 4096)
+    assert qw.qw_mlp_param_count(s) == sum(o * i + o for o, i in W.mlp_layer_sizes(5, 256, 4, 6))
+    assert qw.qw_mlp_workspace_bytes(s) % 256 == 0
+
+
+@pytest.mark.parametrize("shape", [(0, 256, 4, 6, 4, 64), (17, 256, 4, 6, 4, 64), (5, 100, 4, 6, 4, 64),
+                                   (5, 256, 0, 6, 4, 64), (5, 256, 4, 17, 4, 64), (5, 256, 4, 6, 0, 64),
+                                   (5, 256, 4, 6, 4, 0), (5, 2048, 4, 6, 4, 64)])
+def test_mlp_rejects_bad_shapes(shape):
+    with pytest.raises(qw.QWError) as e:
+        qw.qw_mlp_workspace_bytes(qw.qw_mlp_shape(*shape))
+    assert e.value.code == qw.QW_E_SIZE
+
+
+def test_gemm_rejects_bad_arguments_on_host():
+    L = qw.lib()
+    vp = ctypes.c_void_p
+    assert L.qw_gemm_bf16_nt(None, 16, vp(256), 16, vp(256), 16, 4, 4, 16, None) == qw.QW_E_ARG
+    assert L.qw_gemm_bf16_nt(vp(256), 16, vp(256), 16, vp(256), 16, 4, 4, 8, None) == qw.QW_E_SIZE
+    assert L.qw_gemm_bf16_nt(vp(256), 12, vp(256), 16, vp(256), 16, 4, 4, 16, None) == qw.QW_E_ARG
+    assert L.qw_gemm_bf16_nt(vp(264), 16, vp(256), 16, vp(256), 16, 4, 4, 16, None) == qw.QW_E_ARG
