@@ -5,12 +5,15 @@ Bars (bfloat16 unit roundoff u = 2^-8 relative spacing, FP32 accumulation):
 * the product: |C - C_exact| <= 2 K 2^-24 sum_k |a_k b_k| + 1e-30 on bfloat16
   inputs (exact products, FP32 sums of K terms);
 * forward pass and gradients against the oracle with the same bfloat16
-  rounding points: differences come only from FP32-vs-FP64 sums and the rare
-  bfloat16 rounding flips they cause (a flip moves one stored value by one
-  spacing, 2^-8 relative); outputs within 2e-3 of max|y|, each gradient block
-  within 2e-2 relative L2;
+  rounding points: differences come only from FP32-vs-FP64 sums (relative
+  K 2^-24 ~ 1.5e-5 for K = 256) and the rare bfloat16 rounding flips they
+  cause (a flip moves one stored value by one spacing, 2^-8 relative, for
+  about that fraction 1.5e-5 / 2^-8 ~ 0.4% of the values, with random
+  signs); outputs within 5e-4 of max|y|, each gradient block within 1e-3
+  relative L2;
 * against the plain FP64 oracle (no rounding emulation): gradients within
-  8e-2 relative L2 -- the bfloat16 storage itself;
+  2e-2 relative L2 -- the bfloat16 storage itself, a few spacings 2^-8
+  spread over four layers;
 * Adam: the updated FP32 parameters equal the oracle's Adam step on the
   kernel's own gradients to FP32 rounding (4e-6 relative);
 * nets of an ensemble are independent: each net's gradients equal those of a
@@ -89,7 +92,7 @@ def test_forward_matches_oracle():
         ref, _ = M.forward(layers, x, shift, scale, emulate_bf16=True)
         err = np.max(np.abs(y[k] - ref))
         print(f"  net {k}: max |dy| {err:.2e} (max |y| {np.max(np.abs(ref)):.2e})")
-        assert err <= 2e-3 * np.max(np.abs(ref))
+        assert err <= 5e-4 * np.max(np.abs(ref))
     net.close()
 
 
@@ -111,8 +114,8 @@ def test_gradients_match_oracle():
             eb = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
             e64 = np.linalg.norm(gw - fw) / np.linalg.norm(fw)
             print(f"  net {k} layer {li}: dW rel {ew:.2e}, db rel {eb:.2e}, vs plain FP64 {e64:.2e}")
-            assert ew <= 2e-2 and eb <= 2e-2
-            assert e64 <= 8e-2
+            assert ew <= 1e-3 and eb <= 1e-3
+            assert e64 <= 2e-2
     net.close()
 
 
