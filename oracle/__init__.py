@@ -25,6 +25,7 @@ SRC = os.path.join(HERE, "qw_oracle.c")
 BEAM_NONE = 0
 BEAM_STANDING_PARAXIAL = 1
 BEAM_UNIFORM = 2
+BEAM_GAUSSIAN_FULL = 3
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +60,10 @@ class _Packet(ctypes.Structure):
                 ("sigma_x", ctypes.c_double), ("spin", ctypes.c_int)]
 
 
+class _Frame(ctypes.Structure):
+    _fields_ = [("vy", ctypes.c_double), ("a_m", ctypes.c_double)]
+
+
 class _Obs(ctypes.Structure):
     _fields_ = [("band_ref_idx", ctypes.c_int), ("band_half_idx", ctypes.c_int),
                 ("window_idx", ctypes.c_int), ("n_max", ctypes.c_int), ("spin0", ctypes.c_int)]
@@ -86,6 +91,12 @@ def lib():
         L.or_spinor.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.or_spinor.restype = None
         L.or_init_packet.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Packet), dp]
+        L.or_step_n_frame.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Beam), ctypes.POINTER(_Frame), dp,
+                                      ctypes.c_long, ctypes.c_double, ctypes.c_double]
+        L.or_init_packet_frame.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Packet), ctypes.POINTER(_Frame),
+                                           dp]
+        L.or_observables_frame.argtypes = [ctypes.POINTER(_Grid), dp, ctypes.POINTER(_Obs), ctypes.POINTER(_Frame),
+                                           dp, ctypes.c_int]
         L.or_band_index.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_observables.argtypes = [ctypes.POINTER(_Grid), dp, ctypes.POINTER(_Obs), dp, ctypes.c_int]
         for name in ("or_hamiltonian0", "or_kinetic_matrix"):
@@ -151,6 +162,16 @@ class Packet:
 
 
 @dataclass
+class Frame:
+    """Box moving along y with velocity vy, constant gauge vector potential a_m along y."""
+    vy: float = 0.0
+    a_m: float = 0.0
+
+    def cstruct(self):
+        return _Frame(self.vy, self.a_m)
+
+
+@dataclass
 class ObsSpec:
     band_ref_idx: int
     band_half_idx: int
@@ -199,32 +220,47 @@ def beam_eval(beam: Beam, c: float, x: float, y: float, t: float):
     return ax.value, ay.value
 
 
-def init_packet(grid: Grid, packet: Packet) -> np.ndarray:
+def init_packet(grid: Grid, packet: Packet, frame: Frame = None) -> np.ndarray:
     psi = np.zeros((grid.ny, grid.nx, 4), dtype=np.complex128)
     g = grid.cstruct()
     e = packet.cstruct()
-    _check(lib().or_init_packet(ctypes.byref(g), ctypes.byref(e), _ptr(psi)), "init_packet")
+    if frame is None:
+        _check(lib().or_init_packet(ctypes.byref(g), ctypes.byref(e), _ptr(psi)), "init_packet")
+    else:
+        f = frame.cstruct()
+        _check(lib().or_init_packet_frame(ctypes.byref(g), ctypes.byref(e), ctypes.byref(f), _ptr(psi)),
+               "init_packet")
     return psi
 
 
-def step_n(grid: Grid, beam: Beam, psi: np.ndarray, n: int, t0: float, dt: float) -> np.ndarray:
+def step_n(grid: Grid, beam: Beam, psi: np.ndarray, n: int, t0: float, dt: float, frame: Frame = None) -> np.ndarray:
     """Return psi after n split-operator steps from t0 (the input is not modified)."""
     a = np.ascontiguousarray(psi, dtype=np.complex128).copy()
     assert a.shape == (grid.ny, grid.nx, 4)
     g = grid.cstruct()
     b = beam.cstruct()
-    _check(lib().or_step_n(ctypes.byref(g), ctypes.byref(b), _ptr(a), int(n), float(t0), float(dt)),
-           "step_n")
+    if frame is None:
+        rc = lib().or_step_n(ctypes.byref(g), ctypes.byref(b), _ptr(a), int(n), float(t0), float(dt))
+    else:
+        f = frame.cstruct()
+        rc = lib().or_step_n_frame(ctypes.byref(g), ctypes.byref(b), ctypes.byref(f), _ptr(a), int(n), float(t0),
+                                   float(dt))
+    _check(rc, "step_n")
     return a
 
 
-def observables(grid: Grid, psi: np.ndarray, spec: ObsSpec) -> np.ndarray:
+def observables(grid: Grid, psi: np.ndarray, spec: ObsSpec, frame: Frame = None) -> np.ndarray:
     a = np.ascontiguousarray(psi, dtype=np.complex128)
     nb = 2 * spec.n_max + 1
     out = np.zeros(3 * nb + 3, dtype=np.float64)
     g = grid.cstruct()
     o = spec.cstruct()
-    rc = lib().or_observables(ctypes.byref(g), _ptr(a), ctypes.byref(o), _ptr(out), out.size)
+    if frame is None:
+        rc = lib().or_observables(ctypes.byref(g), _ptr(a), ctypes.byref(o), _ptr(out), out.size)
+    else:
+        f = frame.cstruct()
+        rc = lib().or_observables_frame(ctypes.byref(g), _ptr(a), ctypes.byref(o), ctypes.byref(f), _ptr(out),
+                                        out.size)
     if rc not in (0, -5):
         raise RuntimeError(f"oracle observables failed with status {rc}")
     return out

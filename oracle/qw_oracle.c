@@ -241,9 +241,45 @@ static double ramp(const or_beam *b, double c, double t)
     return 1.0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The full Gaussian-beam standing wave (Sec. II.A, Eq. 1a/1b, 2, 3, 4):      */
+/* for d = +1, -1 and r^2 = y^2 (the z = 0 plane),                            */
+/*   A_x,d = -2 d A0 (w0/w) eps (y/w) exp(-r^2/w^2) cos(phi1_d)               */
+/*   A_y,d = -A0 (w0/w) exp(-r^2/w^2) sin(phi_d)                              */
+/*   phi_d  = w t - d kL x + atan(d x / xR) - d x r^2 / (xR w^2)              */
+/*   phi1_d = phi_d + atan(d x / xR)                                          */
+/*   w(x) = w0 sqrt(1 + x^2/xR^2),  xR = kL w0^2 / 2,  eps = 1/(kL w0),       */
+/* summed over d and multiplied by the switch-on f(t).                        */
+/* ------------------------------------------------------------------------ */
+static void gaussian_full(const or_beam *b, double c, double x, double y, double t, double *out_ax, double *out_ay)
+{
+    double kl = 2.0 * OR_PI / b->lambda_l;
+    double om = c * kl;
+    double w0 = b->w0;
+    double eps = 1.0 / (kl * w0);
+    double xr = 0.5 * kl * w0 * w0;
+    double w = w0 * sqrt(1.0 + (x * x) / (xr * xr));
+    double r2 = y * y;
+    double env = (w0 / w) * exp(-r2 / (w * w));
+    double ax = 0.0, ay = 0.0;
+    for (int d = -1; d <= 1; d += 2) {
+        double phi = om * t - d * kl * x + atan(d * x / xr) - d * x * r2 / (xr * w * w);
+        double phi1 = phi + atan(d * x / xr);
+        ay += -b->a0 * env * sin(phi);
+        ax += -2.0 * d * b->a0 * env * eps * (y / w) * cos(phi1);
+    }
+    double f = ramp(b, c, t);
+    *out_ax = b->longitudinal ? ax * f : 0.0;
+    *out_ay = ay * f;
+}
+
 void or_beam_eval(const or_beam *b, double c, double x, double y, double t, double *out_ax, double *out_ay)
 {
     double ax = 0.0, ay = 0.0;
+    if (b->mode == OR_BEAM_GAUSSIAN_FULL) {
+        gaussian_full(b, c, x, y, t, out_ax, out_ay);
+        return;
+    }
     if (b->mode == OR_BEAM_UNIFORM) {
         ax = b->ux;
         ay = b->uy;
@@ -263,11 +299,15 @@ void or_beam_eval(const or_beam *b, double c, double x, double y, double t, doub
 /* Split-operator steps (Eq. 15): V(t_k, dt/2) F^-1 K(dt) F V(t_{k+1}, dt/2)  */
 /* in application order V(t_k,dt/2) first.  t_k = t0 + k dt.                  */
 /* ------------------------------------------------------------------------ */
-static void apply_interaction(const or_grid *g, const or_beam *b, cplx *psi, double t, double tau)
+/* In a frame (vy, a_m) the box coordinate y stands for the lab point y + vy t,
+ * the Hamiltonian in box coordinates is H(p + a_m e_y, A(x, y + vy t, t)) - vy p_y,
+ * and the scalar -vy p_y, diagonal in momentum space, joins the kinetic part:
+ * exp(-i (H0(p + a_m e_y) - vy p_y) tau) = exp(i vy p_y tau) K(p + a_m e_y, tau). */
+static void apply_interaction(const or_grid *g, const or_beam *b, const or_frame *f, cplx *psi, double t, double tau)
 {
 #pragma omp parallel for schedule(static)
     for (int iy = 0; iy < g->ny; iy++) {
-        double y = coord(g->y_min, g->ly, g->ny, iy);
+        double y = coord(g->y_min, g->ly, g->ny, iy) + f->vy * t;
         for (int ix = 0; ix < g->nx; ix++) {
             double x = coord(g->x_min, g->lx, g->nx, ix);
             double ax, ay;
@@ -279,34 +319,44 @@ static void apply_interaction(const or_grid *g, const or_beam *b, cplx *psi, dou
     }
 }
 
-static void apply_kinetic(const or_grid *g, cplx *phi, double tau)
+static void apply_kinetic(const or_grid *g, const or_frame *f, cplx *phi, double tau)
 {
 #pragma omp parallel for schedule(static)
     for (int ky = 0; ky < g->ny; ky++) {
         double py = momentum(g->ly, g->ny, ky);
+        cplx shift = cexp(I * f->vy * py * tau);
         for (int kx = 0; kx < g->nx; kx++) {
             double px = momentum(g->lx, g->nx, kx);
             cplx k[4][4];
-            kinetic_prop(px, py, g->c, tau, k);
+            kinetic_prop(px, py + f->a_m, g->c, tau, k);
+            for (int i = 0; i < 4; i++)
+                for (int j = 0; j < 4; j++) k[i][j] *= shift;
             apply4(k, phi + ((size_t)ky * g->nx + kx) * 4);
         }
     }
 }
 
-int or_step_n(const or_grid *g, const or_beam *b, double *data, long n, double t0, double dt)
+int or_step_n_frame(const or_grid *g, const or_beam *b, const or_frame *f, double *data, long n, double t0,
+                    double dt)
 {
     cplx *psi = (cplx *)data;
     if (!is_pow2(g->nx) || !is_pow2(g->ny) || n < 0) return -1;
     for (long k = 0; k < n; k++) {
         double tk = t0 + (double)k * dt;
         double tk1 = t0 + (double)(k + 1) * dt;
-        apply_interaction(g, b, psi, tk, 0.5 * dt);
+        apply_interaction(g, b, f, psi, tk, 0.5 * dt);
         or_dft2(data, g->nx, g->ny, 4, -1);
-        apply_kinetic(g, psi, dt);
+        apply_kinetic(g, f, psi, dt);
         or_dft2(data, g->nx, g->ny, 4, +1);
-        apply_interaction(g, b, psi, tk1, 0.5 * dt);
+        apply_interaction(g, b, f, psi, tk1, 0.5 * dt);
     }
     return 0;
+}
+
+int or_step_n(const or_grid *g, const or_beam *b, double *data, long n, double t0, double dt)
+{
+    const or_frame lab = {0.0, 0.0};
+    return or_step_n_frame(g, b, &lab, data, n, t0, dt);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -342,7 +392,10 @@ void or_spinor(double px, double py, double c, int s, double *out)
 /*   sp = 1/(2 sigma_x);  psi(r_j) = sum_p phi(p) exp(i p.r_j), normalised    */
 /*   to sum_cells |psi|^2 = 1.                                                */
 /* ------------------------------------------------------------------------ */
-int or_init_packet(const or_grid *g, const or_packet *e, double *data)
+/* In a frame with gauge shift a_m the grid momentum p is canonical; the
+ * packet is centred on the kinetic momentum p0, i.e. on p = p0 - a_m e_y, and
+ * its bispinors are those of the kinetic momentum p + a_m e_y. */
+int or_init_packet_frame(const or_grid *g, const or_packet *e, const or_frame *f, double *data)
 {
     cplx *psi = (cplx *)data;
     if (!is_pow2(g->nx) || !is_pow2(g->ny) || !(e->sigma_x > 0)) return -1;
@@ -351,13 +404,13 @@ int or_init_packet(const or_grid *g, const or_packet *e, double *data)
         double py = momentum(g->ly, g->ny, ky);
         for (int kx = 0; kx < g->nx; kx++) {
             double px = momentum(g->lx, g->nx, kx);
-            double dpx = px - e->p0x, dpy = py - e->p0y;
+            double dpx = px - e->p0x, dpy = py + f->a_m - e->p0y;
             double amp = exp(-(dpx * dpx + dpy * dpy) / (4.0 * sp * sp));
             /* exp(i p.(r_j - r0)) with r_j = r_min + j d: the r_min - r0 part
              * is a per-momentum phase, the j d part is the inverse DFT kernel */
             double ph = px * (g->x_min - e->x0) + py * (g->y_min - e->y0);
             cplx u[4];
-            or_spinor(px, py, g->c, e->spin, (double *)u);
+            or_spinor(px, py + f->a_m, g->c, e->spin, (double *)u);
             for (int i = 0; i < 4; i++) psi[((size_t)ky * g->nx + kx) * 4 + i] = amp * u[i] * cexp(I * ph);
         }
     }
@@ -368,6 +421,12 @@ int or_init_packet(const or_grid *g, const or_packet *e, double *data)
     double s = 1.0 / sqrt(nn);
     for (size_t i = 0; i < (size_t)g->nx * g->ny * 4; i++) psi[i] *= s;
     return 0;
+}
+
+int or_init_packet(const or_grid *g, const or_packet *e, double *data)
+{
+    const or_frame lab = {0.0, 0.0};
+    return or_init_packet_frame(g, e, &lab, data);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -397,6 +456,15 @@ int or_band_index(int kx_signed, int ref_idx, int half_idx, int window_idx)
 
 int or_observables(const or_grid *g, const double *data, const or_obs_spec *o, double *out, int out_len)
 {
+    const or_frame lab = {0.0, 0.0};
+    return or_observables_frame(g, data, o, &lab, out, out_len);
+}
+
+/* With a gauge shift a_m the projections use the bispinors of the kinetic
+ * momentum p + a_m e_y; the diffraction windows are on p_x (unchanged). */
+int or_observables_frame(const or_grid *g, const double *data, const or_obs_spec *o, const or_frame *f, double *out,
+                         int out_len)
+{
     const cplx *psi = (const cplx *)data;
     int nb = 2 * o->n_max + 1;
     if (o->n_max < 0 || o->band_half_idx <= 0 || o->window_idx < 0 || o->window_idx >= o->band_half_idx ||
@@ -418,16 +486,16 @@ int or_observables(const or_grid *g, const double *data, const or_obs_spec *o, d
         double py = momentum(g->ly, g->ny, ky);
         for (int kx = 0; kx < g->nx; kx++) {
             double px = momentum(g->lx, g->nx, kx);
-            const cplx *f = phi + ((size_t)ky * g->nx + kx) * 4;
+            const cplx *q = phi + ((size_t)ky * g->nx + kx) * 4;
             cplx up[4], um[4];
-            or_spinor(px, py, g->c, +1, (double *)up);
-            or_spinor(px, py, g->c, -1, (double *)um);
+            or_spinor(px, py + f->a_m, g->c, +1, (double *)up);
+            or_spinor(px, py + f->a_m, g->c, -1, (double *)um);
             double w = 0.0;
             cplx cp = 0, cm = 0;
             for (int i = 0; i < 4; i++) {
-                w += creal(f[i] * conj(f[i]));
-                cp += conj(up[i]) * f[i];
-                cm += conj(um[i]) * f[i];
+                w += creal(q[i] * conj(q[i]));
+                cp += conj(up[i]) * q[i];
+                cm += conj(um[i]) * q[i];
             }
             double wp = creal(cp * conj(cp)), wm = creal(cm * conj(cm));
             int n = or_band_index(signed_index(kx, g->nx), o->band_ref_idx, o->band_half_idx, o->window_idx);

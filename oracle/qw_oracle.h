@@ -13,7 +13,7 @@
 extern "C" {
 #endif
 
-enum { OR_BEAM_NONE = 0, OR_BEAM_STANDING_PARAXIAL = 1, OR_BEAM_UNIFORM = 2 };
+enum { OR_BEAM_NONE = 0, OR_BEAM_STANDING_PARAXIAL = 1, OR_BEAM_UNIFORM = 2, OR_BEAM_GAUSSIAN_FULL = 3 };
 
 typedef struct {
     int nx, ny;                  /* powers of two */
@@ -31,8 +31,17 @@ typedef struct {
     double ux, uy;       /* OR_BEAM_UNIFORM only: constant A */
 } or_beam;
 
+/* Frame of the simulation: the box moves along y with velocity vy (box
+ * coordinate y is the lab coordinate y - vy t), and a constant vector
+ * potential a_m along y is added to the field (a gauge shift between the
+ * canonical grid momentum p and the kinetic momentum p + a_m e_y). */
 typedef struct {
-    double p0x, p0y;  /* central momentum */
+    double vy;
+    double a_m;
+} or_frame;
+
+typedef struct {
+    double p0x, p0y;  /* central kinetic momentum */
     double x0, y0;    /* central position */
     double sigma_x;   /* position-density standard deviation */
     int spin;         /* +1: chi+ (spin +x), -1: chi- */
@@ -54,10 +63,15 @@ int or_dft2(double *data, int nx, int ny, int ncomp, int sign);
 
 void or_beam_eval(const or_beam *b, double c, double x, double y, double t, double *ax, double *ay);
 int or_step_n(const or_grid *g, const or_beam *b, double *psi, long n, double t0, double dt);
+int or_step_n_frame(const or_grid *g, const or_beam *b, const or_frame *f, double *psi, long n, double t0,
+                    double dt);
 void or_spinor(double px, double py, double c, int s, double *u_out);
 int or_init_packet(const or_grid *g, const or_packet *e, double *psi);
+int or_init_packet_frame(const or_grid *g, const or_packet *e, const or_frame *f, double *psi);
 int or_band_index(int kx_signed, int ref_idx, int half_idx, int window_idx); /* -(1<<30): none */
 int or_observables(const or_grid *g, const double *psi, const or_obs_spec *o, double *out, int out_len);
+int or_observables_frame(const or_grid *g, const double *psi, const or_obs_spec *o, const or_frame *f, double *out,
+                         int out_len);
 
 void or_hamiltonian0(double px, double py, double c, double *out16c);
 void or_kinetic_matrix(double px, double py, double c, double tau, double *out16c);

@@ -236,10 +236,11 @@ int qw_init_grid(qw_ctx* out, const qw_grid* g, void* workspace, size_t ws_bytes
         return fail(nullptr, QW_E_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
     if (ws_bytes < lay.total)
         return fail(nullptr, QW_E_WORKSPACE, "workspace has %zu bytes, the grid needs %zu", ws_bytes, lay.total);
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-        (void)hipGetLastError();
-        return fail(nullptr, QW_E_ARG, "workspace is not device memory");
+    int ws_device = 0;
+    {
+        std::string msg;
+        const int drc = qwh::device_of(workspace, &ws_device, &msg);
+        if (drc != QW_OK) return fail(nullptr, drc, "%s", msg.c_str());
     }
     qw_ctx h = new (std::nothrow) qw_ctx_s;
     if (!h) return fail(nullptr, QW_E_DEVICE, "out of host memory");
@@ -247,7 +248,7 @@ int qw_init_grid(qw_ctx* out, const qw_grid* g, void* workspace, size_t ws_bytes
     h->ws = static_cast<char*>(workspace);
     h->ws_bytes = ws_bytes;
     h->lay = lay;
-    h->device = attr.device;
+    h->device = ws_device;
     hipStream_t s = as_stream(hip_stream);
     hipError_t e = f32(h) ? qw::launch_twiddles_f32(h->ws + lay.twx, g->nx, s)
                           : qw::launch_twiddles_f64(h->ws + lay.twx, g->nx, s);

@@ -470,10 +470,11 @@ int qw_batch_init(qw_batch* out, const qw_instance* inst, int32_t n, void* works
         return bfail(nullptr, QW_E_WORKSPACE, "workspace must be %zu-byte aligned", qwh::kAlign);
     if (ws_bytes < L.total)
         return bfail(nullptr, QW_E_WORKSPACE, "workspace has %zu bytes, the batch needs %zu", ws_bytes, L.total);
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-        (void)hipGetLastError();
-        return bfail(nullptr, QW_E_ARG, "workspace is not device memory");
+    int ws_device = 0;
+    {
+        std::string msg;
+        const int drc = qwh::device_of(workspace, &ws_device, &msg);
+        if (drc != QW_OK) return bfail(nullptr, drc, "%s", msg.c_str());
     }
     qw_batch b = new (std::nothrow) qw_batch_s;
     if (!b) return bfail(nullptr, QW_E_DEVICE, "out of host memory");
@@ -483,7 +484,7 @@ int qw_batch_init(qw_batch* out, const qw_instance* inst, int32_t n, void* works
     b->lay = std::move(L);
     b->ws = static_cast<char*>(workspace);
     b->ws_bytes = ws_bytes;
-    b->device = attr.device;
+    b->device = ws_device;
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cu > 0)
         b->n_cu = cu;

@@ -29,6 +29,25 @@ inline bool finite_all(std::initializer_list<double> v)
     return true;
 }
 
+// The device of a device-accessible allocation (device, managed or unified
+// memory); anything else -- host memory, an unknown pointer -- is refused.
+inline int device_of(const void* p, int* device, std::string* msg)
+{
+    hipPointerAttribute_t attr{};
+    const hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *msg = std::string("workspace is not device memory (pointer attributes: ") + hipGetErrorString(e) + ")";
+        return QW_E_ARG;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged && attr.type != hipMemoryTypeUnified) {
+        *msg = "workspace is not device memory (memory type " + std::to_string((int)attr.type) + ")";
+        return QW_E_ARG;
+    }
+    *device = attr.device;
+    return QW_OK;
+}
+
 inline bool is_pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 
 inline int ilog2(int n)

@@ -12,6 +12,7 @@
 
 #include "qw.h"
 #include "qw_mlp.h"
+#include "qw_host.hpp"
 #include "qw_mlp_launch.hpp"
 
 namespace {
@@ -404,10 +405,11 @@ int qw_mlp_init(qw_mlp* out, const qw_mlp_shape* s, const float* shift, const fl
     Plan p = make_plan(*s);
     if (ws_bytes < p.total)
         return mfail(nullptr, QW_E_WORKSPACE, "workspace has %zu bytes, the network needs %zu", ws_bytes, p.total);
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
-        (void)hipGetLastError();
-        return mfail(nullptr, QW_E_ARG, "workspace is not device memory");
+    int ws_device = 0;
+    {
+        std::string msg;
+        const int drc = qwh::device_of(workspace, &ws_device, &msg);
+        if (drc != QW_OK) return mfail(nullptr, drc, "%s", msg.c_str());
     }
     qw_mlp h = new (std::nothrow) qw_mlp_s;
     if (!h) return mfail(nullptr, QW_E_DEVICE, "out of host memory");

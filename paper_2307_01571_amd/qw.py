@@ -87,6 +87,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_01571_amd.build`")
+    # torch ships its own HIP runtime under another file name; loading torch
+    # first makes the library bind to that same runtime (same SONAME) instead
+    # of a second copy, so both see the same devices and allocations
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
