@@ -56,7 +56,8 @@ enum { QW_F64 = 0, QW_F32 = 1 };
 enum {
     QW_BEAM_NONE = 0,              /* A = 0: free evolution */
     QW_BEAM_STANDING_PARAXIAL = 1, /* standing wave, see qw_beam */
-    QW_BEAM_UNIFORM = 2            /* constant A = (ux, uy) */
+    QW_BEAM_UNIFORM = 2,           /* constant A = (ux, uy) */
+    QW_BEAM_GAUSSIAN_FULL = 3      /* the full two-beam Gaussian standing wave, see qw_beam */
 };
 
 typedef struct qw_ctx_s *qw_ctx;
@@ -74,10 +75,18 @@ typedef struct {
     int32_t precision;
 } qw_grid;
 
-/* Vector potential (Sec. II.A, Eq. 1-4, paraxial limit x << x_R, z = 0):
+/* Vector potential.  QW_BEAM_STANDING_PARAXIAL (Sec. II.A, Eq. 1-4 in the
+ * paraxial limit x << x_R, z = 0):
  *   A_y = a0 exp(-y^2/w0^2) cos(k_L x) cos(w t) f(t)
  *   A_x = a0 (2 y / (k_L w0^2)) exp(-y^2/w0^2) sin(k_L x) cos(w t) f(t)
- * with k_L = 2 pi / lambda_l, w = c k_L, and the switch-on
+ * QW_BEAM_GAUSSIAN_FULL (Sec. II.A, Eq. 1a, 1b, 2, 3 and 4 as printed, with
+ * r^2 = y^2): the sum over d = +1, -1 of
+ *   A_x,d = -2 d a0 (w0/w) eps (y/w) exp(-y^2/w^2) cos(phi_d + atan(d x/x_R))
+ *   A_y,d = -a0 (w0/w) exp(-y^2/w^2) sin(phi_d),
+ *   phi_d = w t - d k_L x + atan(d x/x_R) - d x y^2/(x_R w^2),
+ *   w = w0 sqrt(1 + x^2/x_R^2), x_R = k_L w0^2/2, eps = 1/(k_L w0),
+ * times f(t), evaluated per cell at the lab point of the cell (see qw_frame).
+ * Both: k_L = 2 pi / lambda_l, w = c k_L, and the switch-on
  * f(t) = sin^2(pi t / (2 T_r)) for t < T_r = ramp_periods * lambda_l / c,
  * else 1 (ramp_periods = 0: no ramp).  longitudinal = 0 drops A_x.
  * QW_BEAM_UNIFORM uses the constant (ux, uy) and ignores the rest. */
@@ -88,11 +97,27 @@ typedef struct {
     double ux, uy;
 } qw_beam;
 
+/* Frame of the simulation (Sec. II.D): the box moves along y with velocity
+ * vy -- box row y stands for the lab point y + vy t, so the box follows a
+ * packet moving with vy -- and a constant vector potential a_m along y is
+ * added (the paper's gauge shift between canonical and kinetic momentum:
+ * the grid momentum p is canonical, the kinetic momentum is p + a_m e_y).
+ * In box coordinates H = c alpha.(p + a_m e_y + A(x, y + vy t, t)) + beta c^2
+ * - vy p_y; the scalar -vy p_y joins the kinetic propagator as the phase
+ * exp(i vy p_y dt).  |vy| < c; a moving box (vy != 0) needs a field that is
+ * evaluated per cell (QW_BEAM_NONE, QW_BEAM_UNIFORM or QW_BEAM_GAUSSIAN_FULL).
+ * Default: vy = a_m = 0 (the lab frame, no gauge shift). */
+typedef struct {
+    double vy, a_m;
+} qw_frame;
+
 /* Initial packet (Sec. II.C, Eq. 12-13):
  *   phi(p) = exp(-|p - p0|^2 / (4 s_p^2)) u^s(p) exp(-i p.r0),  s_p = 1/(2 sigma_x),
  * with u^s the unit-normalised positive-energy bispinor of Eq. 9 in the
  * x-polarised basis chi^+ = (1, 1)/sqrt2 (spin = +1) or chi^- = (1, -1)/sqrt2
- * (spin = -1); psi = sum_p phi(p) exp(i p.r), normalised to sum |psi|^2 = 1. */
+ * (spin = -1); psi = sum_p phi(p) exp(i p.r), normalised to sum |psi|^2 = 1.
+ * With a gauge shift a_m (qw_frame), p0 is the kinetic momentum: the packet
+ * sits at grid momentum p0 - a_m e_y with the bispinors of p + a_m e_y. */
 typedef struct {
     double p0x, p0y, x0, y0, sigma_x;
     int32_t spin;
@@ -119,6 +144,10 @@ int qw_init_grid(qw_ctx *out, const qw_grid *g, void *workspace, size_t ws_bytes
  * stream of the next call that needs them). */
 int qw_set_beam(qw_ctx h, const qw_beam *b);
 
+/* Set the frame (host-only; takes effect for the next calls).  The kinetic
+ * table, packets and observables of a context follow its current frame. */
+int qw_set_frame(qw_ctx h, const qw_frame *f);
+
 /* Write the normalised initial packet into psi (several kernels). */
 int qw_init_packet(qw_ctx h, void *psi, const qw_packet *e, void *hip_stream);
 
@@ -133,11 +162,20 @@ int qw_step_n(qw_ctx h, void *psi, int64_t n, double t0, double dt, void *hip_st
  *   [norm, P_n (B), P_n^+ (B), P_n^- (B), P_flip, P_neg],  B = 2 n_max + 1,
  * out_len >= 3B + 3.  norm = sum_cells |psi|^2; every P is a ratio to
  * sum_p |phi(p)|^2: P_n = window sum of |phi|^2, P_n^s = window sum of
- * |<u^s(p)|phi(p)>|^2, P_flip = sum over all p of |<u^{-spin0}|phi>|^2,
+ * |<u^s(p)|phi(p)>|^2 (bispinors of the kinetic momentum p + a_m e_y),
+ * P_flip = sum over all p of |<u^{-spin0}|phi>|^2,
  * P_neg = 1 - sum_p (|c^+|^2 + |c^-|^2) (the negative-energy share).
  * Waits for hip_stream.  Returns QW_E_NUMERIC if any output is not finite. */
 int qw_observables(qw_ctx h, const void *psi, const qw_obs_spec *o, double *out_host, int32_t out_len,
                    void *hip_stream);
+
+/* Momentum-space maps of psi (not modified): out (device memory, out_len >=
+ * 3 nx ny doubles) receives for every momentum cell, laid out [ky][kx][3] in
+ * the transform's order (index k stands for the signed k < n/2 ? k : k - n),
+ * (|phi(p)|^2, |<u^+(p)|phi(p)>|^2, |<u^-(p)|phi(p)>|^2) with phi the
+ * unnormalised forward transform (Eq. 14, 18-19; bispinors of the kinetic
+ * momentum).  Asynchronous. */
+int qw_momentum_maps(qw_ctx h, const void *psi, double *out, int64_t out_len, void *hip_stream);
 
 /* Per-kernel timing for profiling: with enable = 1, every later launch of a
  * row or column pass by qw_step_n is bracketed by HIP events on its stream.
@@ -162,6 +200,9 @@ void qw_destroy(qw_ctx h);
  * replays a captured HIP graph, and the transform schedules are picked per
  * line length by a built-in autotuner.  The physics of each instance is
  * exactly that of the single-instance calls above (same kernels' bodies).
+ *
+ * Batched instances use the lab frame (no qw_frame) and the table-driven
+ * fields (QW_BEAM_NONE, QW_BEAM_STANDING_PARAXIAL, QW_BEAM_UNIFORM).
  *
  * Batch state: the instances' psi arrays back to back in one caller-owned
  * device buffer, instance i at byte offset offsets[i] (256-byte aligned),

@@ -66,16 +66,23 @@ int qw_mlp_set_params(qw_mlp h, const float *params, void *hip_stream);
 /* Copy the current FP32 master parameters to device memory. */
 int qw_mlp_get_params(qw_mlp h, float *params, void *hip_stream);
 
-/* Outputs of every net: x is [B][n_in] FP32, y is [n_nets][B][n_out] FP32
- * (device), 1 <= B <= max_batch. */
+/* Raw outputs of every net (before the output map): x is [B][n_in] FP32,
+ * y is [n_nets][B][n_out] FP32 (device), 1 <= B <= max_batch. */
 int qw_mlp_forward(qw_mlp h, const float *x, int32_t B, float *y, void *hip_stream);
 
-/* Ensemble prediction: mean [B][n_out] over the nets and, per sample, the
- * largest standard deviation over the outputs (the error estimate), spread
- * [B] (both device FP32). */
+/* Output map of qw_mlp_predict (host arrays of n_out floats; waits for
+ * hip_stream): predictions are y scale + shift of the network outputs y, so
+ * a network trained on standardised targets (t - shift) / scale predicts in
+ * the targets' own units.  Default: identity. */
+int qw_mlp_set_output_map(qw_mlp h, const float *shift, const float *scale, void *hip_stream);
+
+/* Ensemble prediction: mean [B][n_out] over the nets of the mapped outputs
+ * and, per sample, the largest standard deviation over the outputs (the
+ * error estimate), spread [B] (both device FP32). */
 int qw_mlp_predict(qw_mlp h, const float *x, int32_t B, float *mean, float *spread, void *hip_stream);
 
-/* Loss and gradients without an update: t is [B][n_out] targets; grads is
+/* Loss and gradients without an update: t is [B][n_out] targets in the
+ * units of the raw outputs (standardised, if an output map is used); grads is
  * laid out as the parameters (n_nets x per_net FP32), loss is [n_nets]
  * (device; either may be NULL). */
 int qw_mlp_gradients(qw_mlp h, const float *x, const float *t, int32_t B, float *grads, float *loss,

@@ -51,8 +51,8 @@ Layout make_layout(const qw_grid& g)
     o = align_up(o + (size_t)g.nx * cs);
     L.by = o;
     o = align_up(o + (size_t)g.ny * cs);
-    L.ktab = o;
-    o = align_up(o + (size_t)(g.nx / 2 + 1) * (g.ny / 2 + 1) * cs);
+    L.ktab = o;  // room for either table: (nx/2+1)(ny/2+1) pairs, or (nx/2+1) ny pairs of pairs in a frame
+    o = align_up(o + (size_t)(g.nx / 2 + 1) * g.ny * 2 * cs);
     L.rownorm = o;
     o = align_up(o + (size_t)g.ny * sizeof(double));
     L.partial = o;
@@ -77,6 +77,8 @@ struct qw_ctx_s {
     bool tables_dirty = true;
     bool ktab_valid = false;
     double ktab_dt = 0.0;  // time step the kinetic table was built for
+    qw_frame frame{};      // moving box and gauge shift (zero: lab frame)
+    qw_frame ktab_frame{}; // frame the kinetic table was built for
     char* ws = nullptr;
     size_t ws_bytes = 0;
     Layout lay{};
@@ -176,13 +178,22 @@ int ensure_tables(qw_ctx h, hipStream_t s)
 // the kinetic table depends on dt only (and the grid): rebuild when dt changes
 int ensure_kinetic_table(qw_ctx h, double dt, hipStream_t s)
 {
-    if (h->ktab_valid && h->ktab_dt == dt) return QW_OK;
-    const qw::KineticArgs k = qwh::kinetic_args(h->g, dt);
+    if (h->ktab_valid && h->ktab_dt == dt && h->ktab_frame.vy == h->frame.vy && h->ktab_frame.a_m == h->frame.a_m)
+        return QW_OK;
+    qw::KineticArgs k = qwh::kinetic_args(h->g, dt);
     void* kt = h->ws + h->lay.ktab;
-    hipError_t e = f32(h) ? qw::launch_kinetic_table_f32(kt, k, s) : qw::launch_kinetic_table_f64(kt, k, s);
+    hipError_t e;
+    if (qwh::frame_active(h->frame)) {
+        k.vy = h->frame.vy;
+        k.a_m = h->frame.a_m;
+        e = f32(h) ? qw::launch_kinetic_table_frame_f32(kt, k, s) : qw::launch_kinetic_table_frame_f64(kt, k, s);
+    } else {
+        e = f32(h) ? qw::launch_kinetic_table_f32(kt, k, s) : qw::launch_kinetic_table_f64(kt, k, s);
+    }
     if (e != hipSuccess) return hip_fail(h, e, "kinetic table kernel");
     h->ktab_valid = true;
     h->ktab_dt = dt;
+    h->ktab_frame = h->frame;
     return QW_OK;
 }
 
@@ -196,7 +207,7 @@ qw::RowArgs row_args(qw_ctx h, const void* src, void* dst)
     a.beam_y = h->ws + h->lay.by;
     a.rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
     a.scale_src = reinterpret_cast<const double*>(h->ws + h->lay.scalars);
-    qwh::row_field(h->g, h->b, h->beam_set, &a);
+    qwh::row_field(h->g, h->b, h->beam_set, &a, h->frame.vy);
     return a;
 }
 
@@ -208,6 +219,8 @@ qw::ColArgs col_args(qw_ctx h, void* psi)
     a.ktab = h->ws + h->lay.ktab;
     qwh::col_grid(h->g, &a);
     a.partial = reinterpret_cast<double*>(h->ws + h->lay.partial);
+    a.frame = qwh::frame_active(h->frame) ? 1 : 0;
+    a.a_m = h->frame.a_m;
     return a;
 }
 
@@ -285,6 +298,17 @@ int qw_set_beam(qw_ctx h, const qw_beam* b)
     return QW_OK;
 }
 
+int qw_set_frame(qw_ctx h, const qw_frame* f)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!f) return fail(h, QW_E_ARG, "frame is NULL");
+    std::string msg;
+    const int rc = qwh::check_frame(*f, h->g.c, &msg);
+    if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
+    h->frame = *f;
+    return QW_OK;
+}
+
 int qw_init_packet(qw_ctx h, void* psi, const qw_packet* e, void* hip_stream)
 {
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
@@ -293,7 +317,7 @@ int qw_init_packet(qw_ctx h, void* psi, const qw_packet* e, void* hip_stream)
     const int rc = qwh::check_packet(*e, &msg);
     if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
     hipStream_t s = as_stream(hip_stream);
-    const qw::PacketArgs p = qwh::packet_args(h->g, *e);
+    const qw::PacketArgs p = qwh::packet_args(h->g, *e, h->frame.a_m);
     double* rownorm = reinterpret_cast<double*>(h->ws + h->lay.rownorm);
     double* total = reinterpret_cast<double*>(h->ws + h->lay.scalars);
     hipError_t err = f32(h) ? qw::launch_packet_f32(psi, rownorm, p, s) : qw::launch_packet_f64(psi, rownorm, p, s);
@@ -312,9 +336,11 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     if (!qwh::finite_all({t0, dt})) return fail(h, QW_E_ARG, "t0 and dt must be finite");
     if (!h->beam_set) return fail(h, QW_E_STATE, "qw_set_beam has not been called");
     if (n == 0) return QW_OK;
+    if (h->frame.vy != 0.0 && h->b.mode == QW_BEAM_STANDING_PARAXIAL)
+        return fail(h, QW_E_STATE, "a moving box needs a field evaluated per cell, not the paraxial tables");
     {
         std::string msg;
-        const int rc = qwh::check_phases(h->g, h->b, true, n, t0, dt, &msg);
+        const int rc = qwh::check_phases(h->g, h->b, true, n, t0, dt, &msg, &h->frame);
         if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
     }
     hipStream_t s = as_stream(hip_stream);
@@ -378,6 +404,22 @@ int qw_observables(qw_ctx h, const void* psi, const qw_obs_spec* o, double* out_
     if (e != hipSuccess) return hip_fail(h, e, "observables");
     for (int i = 0; i < 3 * nb + 3; ++i)
         if (!std::isfinite(out_host[i])) return fail(h, QW_E_NUMERIC, "observable %d is not finite", i);
+    return QW_OK;
+}
+
+int qw_momentum_maps(qw_ctx h, const void* psi, double* out, int64_t out_len, void* hip_stream)
+{
+    if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
+    if (!psi || !out) return fail(h, QW_E_ARG, "psi or out is NULL");
+    const int64_t need = (int64_t)h->g.nx * h->g.ny * 3;
+    if (out_len < need) return fail(h, QW_E_ARG, "out_len %lld < %lld", (long long)out_len, (long long)need);
+    hipStream_t s = as_stream(hip_stream);
+    void* plane = h->ws + h->lay.plane;
+    qw::ColArgs c = col_args(h, plane);
+    c.partial = out;
+    hipError_t e = launch_row(h, qw::ROW_FWD_NORM, row_args(h, psi, plane), s);
+    if (e == hipSuccess) e = launch_col(h, qw::COL_MAPS, c, s);
+    if (e != hipSuccess) return hip_fail(h, e, "momentum maps");
     return QW_OK;
 }
 

@@ -122,6 +122,10 @@ int make_batch_layout(const qw_instance* inst, int n, BatchLayout* L, std::strin
             rc = QW_E_ARG;
         }
         if (rc == QW_OK) rc = qwh::check_beam(inst[i].beam, &m);
+        if (rc == QW_OK && inst[i].beam.mode == QW_BEAM_GAUSSIAN_FULL) {
+            m = "batched instances take the table-driven fields (not QW_BEAM_GAUSSIAN_FULL)";
+            rc = QW_E_ARG;
+        }
         if (rc != QW_OK) {
             *msg = "instance " + std::to_string(i) + ": " + m;
             return rc;

@@ -78,15 +78,17 @@ inline int check_grid(const qw_grid& g, int lo, int hi, std::string* msg)
     return QW_OK;
 }
 
+inline bool standing(int mode) { return mode == QW_BEAM_STANDING_PARAXIAL || mode == QW_BEAM_GAUSSIAN_FULL; }
+
 inline int check_beam(const qw_beam& b, std::string* msg)
 {
-    if (b.mode != QW_BEAM_NONE && b.mode != QW_BEAM_STANDING_PARAXIAL && b.mode != QW_BEAM_UNIFORM) {
+    if (b.mode != QW_BEAM_NONE && b.mode != QW_BEAM_STANDING_PARAXIAL && b.mode != QW_BEAM_UNIFORM &&
+        b.mode != QW_BEAM_GAUSSIAN_FULL) {
         *msg = "unknown beam mode " + std::to_string(b.mode);
         return QW_E_ARG;
     }
-    if (b.mode == QW_BEAM_STANDING_PARAXIAL &&
-        (!finite_all({b.a0, b.lambda_l, b.w0, b.ramp_periods}) || !(b.lambda_l > 0) || !(b.w0 > 0) ||
-         b.ramp_periods < 0)) {
+    if (standing(b.mode) && (!finite_all({b.a0, b.lambda_l, b.w0, b.ramp_periods}) || !(b.lambda_l > 0) ||
+                             !(b.w0 > 0) || b.ramp_periods < 0)) {
         *msg = "standing wave needs finite a0, lambda_l > 0, w0 > 0, ramp_periods >= 0";
         return QW_E_ARG;
     }
@@ -123,13 +125,24 @@ inline int check_obs(const qw_obs_spec& o, std::string* msg)
     return QW_OK;
 }
 
-// the phases w t and E dt of a run of n steps must stay in the exact range
-// of the in-kernel reduction
+inline int check_frame(const qw_frame& f, double c, std::string* msg)
+{
+    if (!finite_all({f.vy, f.a_m}) || !(std::fabs(f.vy) < c)) {
+        *msg = "frame needs finite vy and a_m with |vy| < c";
+        return QW_E_ARG;
+    }
+    return QW_OK;
+}
+
+inline bool frame_active(const qw_frame& f) { return f.vy != 0.0 || f.a_m != 0.0; }
+
+// the phases w t, E dt and vy p_y dt of a run of n steps must stay in the
+// exact range of the in-kernel reduction
 inline int check_phases(const qw_grid& g, const qw_beam& b, bool beam_on, int64_t n, double t0, double dt,
-                        std::string* msg)
+                        std::string* msg, const qw_frame* f = nullptr)
 {
     char buf[256];
-    if (beam_on && b.mode == QW_BEAM_STANDING_PARAXIAL) {
+    if (beam_on && standing(b.mode)) {
         const double om = g.c * 2.0 * kPi / b.lambda_l;
         const double tmax = std::fmax(std::fabs(t0), std::fabs(t0 + (double)n * dt));
         if (om * tmax > kMaxPhase) {
@@ -138,8 +151,13 @@ inline int check_phases(const qw_grid& g, const qw_beam& b, bool beam_on, int64_
             return QW_E_ARG;
         }
     }
-    const double px = 0.5 * g.nx * 2.0 * kPi / g.lx, py = 0.5 * g.ny * 2.0 * kPi / g.ly;
+    const double px = 0.5 * g.nx * 2.0 * kPi / g.lx;
+    const double py = 0.5 * g.ny * 2.0 * kPi / g.ly + (f ? std::fabs(f->a_m) : 0.0);
     const double emax = g.c * std::sqrt(g.c * g.c + px * px + py * py);
+    if (f && std::fabs(f->vy) * py * std::fabs(dt) > kMaxPhase) {
+        *msg = "|vy p_y dt| exceeds the phase range";
+        return QW_E_ARG;
+    }
     if (emax * std::fabs(dt) > kMaxPhase) {
         snprintf(buf, sizeof buf, "|E dt| = %g exceeds %g", emax * std::fabs(dt), kMaxPhase);
         *msg = buf;
@@ -180,7 +198,7 @@ inline qw::KineticArgs kinetic_args(const qw_grid& g, double dt)
     return k;
 }
 
-inline qw::PacketArgs packet_args(const qw_grid& g, const qw_packet& e)
+inline qw::PacketArgs packet_args(const qw_grid& g, const qw_packet& e, double a_m = 0.0)
 {
     qw::PacketArgs p{};
     p.nx = g.nx;
@@ -196,17 +214,32 @@ inline qw::PacketArgs packet_args(const qw_grid& g, const qw_packet& e)
     p.sigma_x = e.sigma_x;
     p.x_min = g.x_min;
     p.y_min = g.y_min;
+    p.a_m = a_m;
     return p;
 }
 
 // field and grid parts of the row-pass arguments (tables and state set by the caller)
-inline void row_field(const qw_grid& g, const qw_beam& b, bool beam_on, qw::RowArgs* a)
+inline void row_field(const qw_grid& g, const qw_beam& b, bool beam_on, qw::RowArgs* a, double vy = 0.0)
 {
     a->beam_mode = beam_on ? b.mode : QW_BEAM_NONE;
-    if (b.mode == QW_BEAM_STANDING_PARAXIAL) {
+    if (standing(b.mode)) {
         a->omega = g.c * 2.0 * kPi / b.lambda_l;
         a->t_ramp = b.ramp_periods * b.lambda_l / g.c;
         a->ramp_k = a->t_ramp > 0 ? kPi / (2.0 * a->t_ramp) : 0.0;
+    }
+    if (b.mode == QW_BEAM_GAUSSIAN_FULL) {
+        qw::FullBeam& f = a->full;
+        f.a0 = b.a0;
+        f.kl = 2.0 * kPi / b.lambda_l;
+        f.w0 = b.w0;
+        f.xr = 0.5 * f.kl * b.w0 * b.w0;
+        f.eps = 1.0 / (f.kl * b.w0);
+        f.x_min = g.x_min;
+        f.dx = g.lx / g.nx;
+        f.y_min = g.y_min;
+        f.dy = g.ly / g.ny;
+        f.vy = vy;
+        f.longitudinal = b.longitudinal;
     }
     a->c = g.c;
     a->ny = g.ny;

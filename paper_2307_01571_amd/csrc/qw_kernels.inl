@@ -165,6 +165,47 @@ __device__ __forceinline__ void apply_interaction(cx<T> (&v)[2][E], const cx<T>*
     }
 }
 
+// The full Gaussian-beam standing wave (Sec. II.A, Eq. 1-4) at z = 0, per
+// cell in double.  With Phi = kL x - G + x y^2/(xR w^2), G = atan(x/xR), the
+// sums over the two beams d = +-1 of Eq. 1b and 1a are
+//   A_y = -2 A0 (w0/w) exp(-y^2/w^2) sin(w t) cos(Phi),
+//   A_x = -4 A0 eps (w0/w) (y/w) exp(-y^2/w^2) sin(w t) sin(Phi - G),
+// times the switch-on f(t); y is the lab coordinate of the row.
+template <typename T, int E, int NT>
+__device__ __forceinline__ void apply_full_beam(cx<T> (&v)[2][E], const RowArgs& a, int y, int t, double tk, T ctau)
+{
+    const FullBeam& b = a.full;
+    double st, ct;
+    sincos_phase(a.omega * tk, st, ct);
+    if (a.t_ramp > 0.0 && tk < a.t_ramp) {
+        double rs, rc;
+        sincos_phase(a.ramp_k * tk, rs, rc);
+        st *= rs * rs;
+    }
+    const double yl = b.y_min + b.dy * (double)y + b.vy * tk;
+    const double y2 = yl * yl;
+    int tt = t;
+    asm volatile("" : "+v"(tt));
+#pragma unroll 2
+    for (int m = 0; m < E; ++m) {
+        const double x = b.x_min + b.dx * (double)(tt + NT * m);
+        const double q = x / b.xr;
+        const double u = 1.0 + q * q;               // (w/w0)^2
+        const double w2 = b.w0 * b.w0 * u;
+        const double g = atan(q);
+        const double env = exp(-y2 / w2) / sqrt(u) * st;
+        const double phi = b.kl * x - g + x * y2 / (b.xr * w2);
+        double sp, cp, s1, c1;
+        sincos_phase(phi, sp, cp);
+        sincos_phase(phi - g, s1, c1);
+        const T ay = (T)(-2.0 * b.a0 * env * cp);
+        const T ax = b.longitudinal ? (T)(-4.0 * b.a0 * b.eps * env * (yl / sqrt(w2)) * s1) : (T)0;
+        T C, Sn;
+        interaction_coeffs<0>(ax, ay, ctau, C, Sn);
+        block_prop(v[0][m], v[1][m], C, (T)0, Sn * ax, Sn * ay);
+    }
+}
+
 __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k : k - n; }
 
 // ---------------------------------------------------------------------------
@@ -173,7 +214,7 @@ __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k :
 // One tile of RPW rows of length N (transform with E elements per lane and
 // the radix schedule SCH, LDS stride LL per lane group), threads
 // 0 .. RPW 2 N/E - 1.  lds holds RPW 2 LL elements.
-template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE>
+template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE, int BEAM = 0>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds, int tid)
 {
     constexpr int NT = N / E, L = 2 * NT;
@@ -224,7 +265,11 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds,
     if constexpr (MODE == ROW_MID || MODE == ROW_LAST || MODE == ROW_INV_SCALE)
         fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
 
-    if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_LAST) {
+    if constexpr ((MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_LAST) && BEAM == 1) {
+        // interaction propagator V(t, tau) with the full beam evaluated per cell
+        const double tk = a.t0 + (double)a.k * a.dt;
+        apply_full_beam<T, E, NT>(v, a, live ? y : 0, t, tk, (T)(a.c * a.tau_frac * a.dt));
+    } else if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_LAST) {
         // interaction propagator V(t, tau) with A evaluated from the field tables;
         // |A|^2 <= s(t)^2 (Y0^2 + Y1^2) on this row bounds the angle
         const double tk = a.t0 + (double)a.k * a.dt;
@@ -255,12 +300,12 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds,
     for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rd, lane, m * NT * CB);
 }
 
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, int BEAM = 0>
 __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_ROW))) void row_pass(RowArgs a)
 {
     using S = shape<T, N>;
     __shared__ cx<T> lds[S::RPW * 2 * S::LLR];
-    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE>(a, blockIdx.x, lds, threadIdx.x);
+    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM>(a, blockIdx.x, lds, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -268,7 +313,7 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
 // ---------------------------------------------------------------------------
 // One tile of TX columns of length N, threads 0 .. TX 2 N/E - 1; lds holds
 // TX 2 LL elements.
-template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE>
+template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE, int FRAME = 0>
 __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds, int tid)
 {
     constexpr int NT = N / E, L = 2 * NT;
@@ -305,7 +350,28 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
     const int kxs = signed_idx(live ? x : 0, a.nx);
     const double px = a.dkx * (double)kxs;
 
-    if constexpr (MODE == COL_PROP) {
+    if constexpr (MODE == COL_PROP && FRAME == 1) {
+        // in a frame: K(p + a_m e_y, dt) exp(i vy p_y dt) / (nx ny), from the frame
+        // table at (|kx|, ky): ((cos(E dt), sin(E dt)/E)/(nx ny), (cos, sin)(vy p_y dt)),
+        // E of the kinetic momentum (px, py + a_m)
+        const cx2<T>* kt = reinterpret_cast<const cx2<T>*>(a.ktab) + (size_t)(kxs < 0 ? -kxs : kxs) * N;
+        const T sgn = blk ? (T)-1 : (T)1;
+        const T ka = sgn * (T)(c * c);
+        const T kx = (T)(c * px);
+        asm volatile("" ::: "memory");
+        int tt = t;
+        asm volatile("" : "+v"(tt));
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int ky = tt + NT * m;
+            const double pyk = a.dky * (double)signed_idx(ky, N) + a.a_m;
+            const cx2<T> q = kt[ky];
+            block_prop(v[0][m], v[1][m], q.a.re, q.a.im * ka, q.a.im * kx, q.a.im * (T)(c * pyk));
+            v[0][m] = mul(v[0][m], q.b);
+            v[1][m] = mul(v[1][m], q.b);
+        }
+        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
+    } else if constexpr (MODE == COL_PROP) {
         // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny):
         // the table holds (cos(E dt), sin(E dt)/E)/(nx ny) at (|kx|, |ky|) (E depends on
         // |p| only); the matrix entries are (a, bx, by) = sin(E dt)/E (c^2, c px, c py)
@@ -332,7 +398,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
         for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rp, lane, m * mstride);
     }
 
-    if constexpr (MODE == COL_OBS) {
+    if constexpr (MODE == COL_OBS || MODE == COL_MAPS) {
         // spin projections onto the unit bispinors u^+-(p) (Eq. 9, 18):
         //   c^s = sqrt((E + c^2)/(2E)) (aA + s aB)/sqrt2,
         //   aA = phi1 + k (px - i py) phi4,  aB = phi2 + k (px + i py) phi3,  k = c/(E + c^2)
@@ -343,7 +409,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int kys = signed_idx(t + NT * m, N);
-            const double py = a.dky * (double)kys;
+            const double py = a.dky * (double)kys + a.a_m;  // kinetic momentum
             const double en = c * sqrt(c * c + px * px + py * py);
             const double kk = c / (en + c * c);
             const double tr = v[0][m].re, ti = v[0][m].im, br = v[1][m].re, bi = v[1][m].im;
@@ -351,6 +417,20 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
             const double ur = blk ? br : tr, ui = blk ? bi : ti, wr = blk ? tr : br, wi = blk ? ti : bi;
             const double ar = ur + kk * (px * wr + sg * py * wi), ai = ui + kk * (px * wi - sg * py * wr);
             const double or_ = __shfl_xor(ar, 1), oi = __shfl_xor(ai, 1);
+            if constexpr (MODE == COL_MAPS) {
+                // per cell: the pair's two lanes hold the two blocks of one cell
+                const double wl = tr * tr + ti * ti + br * br + bi * bi;
+                const double wo = __shfl_xor(wl, 1);
+                if (live && blk == 0) {
+                    const double nn = (en + c * c) / (4.0 * en);
+                    const double pr = ar + or_, pi = ai + oi, mr = ar - or_, mi = ai - oi;
+                    double* out = a.partial + ((size_t)(t + NT * m) * a.nx + x) * 3;
+                    out[0] = wl + wo;
+                    out[1] = nn * (pr * pr + pi * pi);
+                    out[2] = nn * (mr * mr + mi * mi);
+                }
+                continue;
+            }
             if (live) {
                 sw += tr * tr + ti * ti + br * br + bi * bi;
                 if (blk == 0) {
@@ -361,6 +441,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
                 }
             }
         }
+        if constexpr (MODE == COL_MAPS) return;
         __syncthreads();  // LDS reused for the reduction
         double* red = reinterpret_cast<double*>(lds);
         constexpr int nthr = TX * L;
@@ -405,7 +486,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
     }
 }
 
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, int FRAME = 0>
 __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_COL))) void col_pass(ColArgs a)
 {
     using S = shape<T, N>;
@@ -414,7 +495,7 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     // give each XCD a contiguous run of tiles -- neighbouring tiles share
     // cache lines and then meet in the same L2
     const int tile = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
-    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE>(a, tile, lds, threadIdx.x);
+    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE, FRAME>(a, tile, lds, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -497,6 +578,27 @@ __global__ void kinetic_table(cx<T>* kt, KineticArgs k)
     kt[i] = cx<T>{(T)(c * k.inv_cells), (T)(s / en * k.inv_cells)};
 }
 
+// kinetic table in a frame: for |kx| <= nx/2 and every ky (signed order),
+// ((cos(E dt), sin(E dt)/E)/(nx ny), (cos, sin)(vy py dt)) with py the
+// canonical momentum and E = c sqrt(c^2 + px^2 + (py + a_m)^2); phases in
+// double, reduced in double
+template <typename T>
+__global__ void kinetic_table_frame(cx2<T>* kt, KineticArgs k)
+{
+    const int nx2 = k.nx / 2 + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx2 * k.ny) return;
+    const int ix = i / k.ny, iy = i - ix * k.ny;
+    const double px = k.dkx * (double)ix;
+    const double py = k.dky * (double)(iy < k.ny / 2 ? iy : iy - k.ny);
+    const double pk = py + k.a_m;
+    const double en = k.c * sqrt(k.c * k.c + px * px + pk * pk);
+    double s, c, fs, fc;
+    sincos_phase(en * k.dt, s, c);
+    sincos_phase(k.vy * py * k.dt, fs, fc);
+    kt[i] = cx2<T>{cx<T>{(T)(c * k.inv_cells), (T)(s / en * k.inv_cells)}, cx<T>{(T)fc, (T)fs}};
+}
+
 // ---------------------------------------------------------------------------
 // initial packet in momentum space: phi(p) = g(p) u^s(p) exp(i p.(r_min - r0)),
 // one workgroup per momentum row ky; row sums of |phi|^2 to rownorm[ky]
@@ -514,17 +616,18 @@ __global__ __launch_bounds__(256) void packet_momentum(cx<T>* psi, double* rowno
     double acc = 0.0;
     for (int kx = threadIdx.x; kx < e.nx; kx += blockDim.x) {
         const double px = e.dkx * (double)signed_idx(kx, e.nx);
-        const double dx = px - e.p0x, dy = py - e.p0y;
+        const double pk = py + e.a_m;  // kinetic p_y
+        const double dx = px - e.p0x, dy = pk - e.p0y;
         const double amp = exp(-(dx * dx + dy * dy) / (4.0 * sp * sp));
-        const double en = c * sqrt(c * c + px * px + py * py);
+        const double en = c * sqrt(c * c + px * px + pk * pk);
         const double nrm = sqrt((en + c * c) / (2.0 * en));
         const double kk = c / (en + c * c);
         double sn, cs;
         sincos(px * (e.x_min - e.x0) + py * (e.y_min - e.y0), &sn, &cs);
-        // u = nrm (chi1, chi2, k (px - i py) chi2, k (px + i py) chi1)
+        // u = nrm (chi1, chi2, k (px - i py) chi2, k (px + i py) chi1), kinetic momentum
         const double u1 = nrm * chi1, u2 = nrm * chi2;
-        const double u3r = nrm * kk * px * chi2, u3i = -nrm * kk * py * chi2;
-        const double u4r = nrm * kk * px * chi1, u4i = nrm * kk * py * chi1;
+        const double u3r = nrm * kk * px * chi2, u3i = -nrm * kk * pk * chi2;
+        const double u4r = nrm * kk * px * chi1, u4i = nrm * kk * pk * chi1;
         const double ar = amp * cs, ai = amp * sn;
         cx<T>* q = psi + ((size_t)ky * e.nx + kx) * 4;
         q[0] = cx<T>{(T)(u1 * ar), (T)(u1 * ai)};
@@ -550,6 +653,17 @@ hipError_t row_launch_n(int mode, const RowArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
     const dim3 grid((a.ny + S::RPW - 1) / S::RPW), block(S::RPW * S::L);
+    if (a.beam_mode == QW_BEAM_GAUSSIAN_FULL_) {
+        switch (mode) {
+        case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST, 1>), grid, block, 0, st, a); break;
+        case ROW_MID: hipLaunchKernelGGL((row_pass<T, N, ROW_MID, 1>), grid, block, 0, st, a); break;
+        case ROW_LAST: hipLaunchKernelGGL((row_pass<T, N, ROW_LAST, 1>), grid, block, 0, st, a); break;
+        case ROW_FWD_NORM: hipLaunchKernelGGL((row_pass<T, N, ROW_FWD_NORM>), grid, block, 0, st, a); break;
+        case ROW_INV_SCALE: hipLaunchKernelGGL((row_pass<T, N, ROW_INV_SCALE>), grid, block, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (mode) {
     case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST>), grid, block, 0, st, a); break;
     case ROW_MID: hipLaunchKernelGGL((row_pass<T, N, ROW_MID>), grid, block, 0, st, a); break;
@@ -567,9 +681,13 @@ hipError_t col_launch_n(int mode, const ColArgs& a, hipStream_t st)
     using S = shape<T, N>;
     const dim3 grid((a.nx + S::TX - 1) / S::TX), block(S::TX * S::L);
     switch (mode) {
-    case COL_PROP: hipLaunchKernelGGL((col_pass<T, N, COL_PROP>), grid, block, 0, st, a); break;
+    case COL_PROP:
+        if (a.frame) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((col_pass<T, N, COL_PROP>), grid, block, 0, st, a);
+        break;
     case COL_INV: hipLaunchKernelGGL((col_pass<T, N, COL_INV>), grid, block, 0, st, a); break;
     case COL_OBS: hipLaunchKernelGGL((col_pass<T, N, COL_OBS>), grid, block, 0, st, a); break;
+    case COL_MAPS: hipLaunchKernelGGL((col_pass<T, N, COL_MAPS>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -656,6 +774,15 @@ hipError_t launch_kinetic_table(void* kt, const KineticArgs& k, hipStream_t st)
 }
 
 template <typename T>
+hipError_t launch_kinetic_table_frame(void* kt, const KineticArgs& k, hipStream_t st)
+{
+    const int n = (k.nx / 2 + 1) * k.ny;
+    hipLaunchKernelGGL(kinetic_table_frame<T>, dim3((n + 255) / 256), dim3(256), 0, st, reinterpret_cast<cx2<T>*>(kt),
+                       k);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_packet(void* psi, double* rownorm, const PacketArgs& e, hipStream_t st)
 {
     hipLaunchKernelGGL(packet_momentum<T>, dim3(e.ny), dim3(256), 0, st, reinterpret_cast<cx<T>*>(psi), rownorm, e);
@@ -687,5 +814,9 @@ hipError_t launch_packet(void* psi, double* rownorm, const PacketArgs& e, hipStr
     hipError_t launch_kinetic_table_##SUF(void* kt, const KineticArgs& k, hipStream_t s)                     \
     {                                                                                                        \
         return launch_kinetic_table<T>(kt, k, s);                                                            \
+    }                                                                                                        \
+    hipError_t launch_kinetic_table_frame_##SUF(void* kt, const KineticArgs& k, hipStream_t s)               \
+    {                                                                                                        \
+        return launch_kinetic_table_frame<T>(kt, k, s);                                                      \
     }                                                                                                        \
     }

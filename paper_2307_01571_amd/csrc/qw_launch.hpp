@@ -8,12 +8,22 @@
 namespace qw {
 
 enum { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2, ROW_FWD_NORM = 3, ROW_INV_SCALE = 4 };
-enum { COL_PROP = 0, COL_INV = 1, COL_OBS = 2 };
+enum { COL_PROP = 0, COL_INV = 1, COL_OBS = 2, COL_MAPS = 3 };
 
 // same values as the QW_BEAM_* constants of the public header
 constexpr int QW_BEAM_NONE_ = 0;
 constexpr int QW_BEAM_STANDING_PARAXIAL_ = 1;
 constexpr int QW_BEAM_UNIFORM_ = 2;
+constexpr int QW_BEAM_GAUSSIAN_FULL_ = 3;
+
+// Full Gaussian-beam standing wave, evaluated per cell (double), in a box
+// whose y coordinate stands for the lab point y + vy t.
+struct FullBeam {
+    double a0, kl, w0, xr, eps;  // eps = 1/(kl w0), xr = kl w0^2/2
+    double x_min, dx, y_min, dy;
+    double vy;
+    int longitudinal;
+};
 
 struct RowArgs {
     const void* src;          // [ny][nx][4] complex T
@@ -29,15 +39,20 @@ struct RowArgs {
     double omega, t_ramp, ramp_k, c;  // ramp_k = pi / (2 t_ramp)
     int beam_mode;
     int ny;
+    FullBeam full;            // beam_mode == QW_BEAM_GAUSSIAN_FULL_
 };
 
 struct ColArgs {
     void* psi;
     const void* twy;   // per-pass twiddles of the y transform (2 ny entries)
-    const void* ktab;  // COL_PROP: kinetic table, (nx/2+1) x (ny/2+1) pairs (cos(E dt), sin(E dt)/E)/(nx ny)
+    const void* ktab;  // COL_PROP: kinetic table, (nx/2+1) x (ny/2+1) pairs (cos(E dt), sin(E dt)/E)/(nx ny);
+                       // with a frame (nx/2+1) x ny pairs of pairs, see kinetic_table_frame
     int nx;
+    int frame;         // 1: moving box and/or gauge shift (a_m) -- the frame kinetic table
+    double a_m;        // constant gauge vector potential along y (kinetic p_y = p_y + a_m)
     double dkx, dky, c, dt, inv_cells;
-    double* partial;  // COL_OBS: per-workgroup sums, partial_stride doubles each
+    double* partial;  // COL_OBS: per-workgroup sums, partial_stride doubles each;
+                      // COL_MAPS: [ny][nx][3] per-cell (|phi|^2, |c+|^2, |c-|^2)
     int partial_stride;
     int band_ref, band_half, window, n_max, spin0;
 };
@@ -50,11 +65,13 @@ struct BeamArgs {
 struct KineticArgs {
     int nx, ny;
     double dkx, dky, c, dt, inv_cells;
+    double vy, a_m;  // frame (kinetic_table_frame only)
 };
 
 struct PacketArgs {
     int nx, ny, spin;
     double dkx, dky, c, p0x, p0y, x0, y0, sigma_x, x_min, y_min;
+    double a_m;  // gauge shift: p0 is kinetic, the grid momentum canonical
 };
 
 // ---------------------------------------------------------------------------
@@ -112,6 +129,7 @@ struct BatchLaunch {
     hipError_t launch_beam_tables_##SUF(void* bx, void* by, const BeamArgs& b, hipStream_t s); \
     hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s); \
     hipError_t launch_kinetic_table_##SUF(void* ktab, const KineticArgs& k, hipStream_t s);          \
+    hipError_t launch_kinetic_table_frame_##SUF(void* ktab, const KineticArgs& k, hipStream_t s);    \
     /* batched form (qw_batch_*.hip): lengths 2^lg, lg_min <= lg <= lg_max; schedule variant v */  \
     int batch_lg_min_##SUF();                                                                    \
     int batch_lg_max_##SUF();                                                                    \

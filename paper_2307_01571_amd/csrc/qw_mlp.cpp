@@ -39,7 +39,7 @@ struct Plan {
     int Mpad = 0;          // batch rows, padded
     std::vector<Layer> layer;
     // byte offsets
-    size_t P, Mo, V, G, Wb, Wt, shift, scale, Xb, Xt, Z, H, Ht, Y, dYb, dYt, dZb, dZt, loss_part, loss;
+    size_t P, Mo, V, G, Wb, Wt, shift, scale, oshift, oscale, Xb, Xt, Z, H, Ht, Y, dYb, dYt, dZb, dZt, loss_part, loss;
     size_t total;
 };
 
@@ -101,6 +101,8 @@ Plan make_plan(const qw_mlp_shape& s)
     p.Wt = take(2 * nets * p.nwb);
     p.shift = take(4 * kInPad);
     p.scale = take(4 * kInPad);
+    p.oshift = take(4 * kInPad);
+    p.oscale = take(4 * kInPad);
     p.Xb = take(2 * M * kInPad);
     p.Xt = take(2 * M * kInPad);
     p.Z = take(4 * nets * D * M * W);
@@ -416,16 +418,21 @@ int qw_mlp_init(qw_mlp* out, const qw_mlp_shape* s, const float* shift, const fl
     h->p = p;
     h->ws = static_cast<char*>(workspace);
     hipStream_t st = as_stream(hip_stream);
-    float map[2 * kInPad] = {};
+    float map[4 * kInPad] = {};
     for (int i = 0; i < s->n_in; ++i) {
         map[i] = shift[i];
         map[kInPad + i] = scale[i];
     }
+    for (int i = 0; i < kInPad; ++i) map[3 * kInPad + i] = 1.0f;  // output map: identity
     // zero everything (the paddings of weights and activations must read as zero)
     hipError_t e = qwm::launch_fill_zero(h->ws, p.total, st);
     if (e == hipSuccess) e = hipMemcpyAsync(at<float>(h, p.shift), map, 4 * kInPad, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(at<float>(h, p.scale), map + kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<float>(h, p.oshift), map + 2 * kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<float>(h, p.oscale), map + 3 * kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         mfail(nullptr, QW_E_DEVICE, "network set-up: %s", hipGetErrorString(e));
@@ -449,6 +456,27 @@ int qw_mlp_set_params(qw_mlp h, const float* params, void* hip_stream)
     if (e == hipSuccess) e = qwm::launch_adam(adam_args(h, 0, 0.0f), p.s.n_nets, s);
     if (e != hipSuccess) return mhip(h, e, "set params");
     h->t = 0;
+    return QW_OK;
+}
+
+int qw_mlp_set_output_map(qw_mlp h, const float* shift, const float* scale, void* hip_stream)
+{
+    if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
+    if (!shift || !scale) return mfail(h, QW_E_ARG, "shift or scale is NULL");
+    float map[2 * kInPad] = {};
+    for (int i = 0; i < kInPad; ++i) map[kInPad + i] = 1.0f;
+    for (int i = 0; i < h->p.s.n_out; ++i) {
+        if (!std::isfinite(shift[i]) || !std::isfinite(scale[i]))
+            return mfail(h, QW_E_ARG, "output map entry %d is not finite", i);
+        map[i] = shift[i];
+        map[kInPad + i] = scale[i];
+    }
+    hipStream_t st = as_stream(hip_stream);
+    hipError_t e = hipMemcpyAsync(at<float>(h, h->p.oshift), map, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<float>(h, h->p.oscale), map + kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return mhip(h, e, "output map");
     return QW_OK;
 }
 
@@ -492,7 +520,7 @@ int qw_mlp_predict(qw_mlp h, const float* x, int32_t B, float* mean, float* spre
     hipError_t e = forward(h, x, nullptr, B, s);
     if (e == hipSuccess)
         e = qwm::launch_ensemble(at<float>(h, p.Y), (long long)p.Mpad * kInPad, kInPad, B, p.s.n_out, p.s.n_nets,
-                                 mean, spread, s);
+                                 at<float>(h, p.oshift), at<float>(h, p.oscale), mean, spread, s);
     if (e != hipSuccess) return mhip(h, e, "predict");
     return QW_OK;
 }

@@ -208,20 +208,22 @@ __global__ void loss_finish(const float* part, long long s_part, int n_part, flo
     }
 }
 
-// ensemble mean and spread (largest standard deviation over the outputs)
+// ensemble mean and spread (largest standard deviation over the outputs) of
+// the mapped outputs y oscale + oshift
 __global__ __launch_bounds__(256) void ensemble(const float* y, long long s_net, int ld, int B, int n_out, int nets,
-                                                float* mean, float* spread)
+                                                const float* oshift, const float* oscale, float* mean, float* spread)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= B) return;
     float worst = 0.0f;
     for (int o = 0; o < n_out; ++o) {
+        const float sh = oshift[o], sc = oscale[o];
         float s = 0.0f;
-        for (int k = 0; k < nets; ++k) s += y[k * s_net + (size_t)m * ld + o];
+        for (int k = 0; k < nets; ++k) s += y[k * s_net + (size_t)m * ld + o] * sc + sh;
         const float mu = s / nets;
         float q = 0.0f;
         for (int k = 0; k < nets; ++k) {
-            const float d = y[k * s_net + (size_t)m * ld + o] - mu;
+            const float d = y[k * s_net + (size_t)m * ld + o] * sc + sh - mu;
             q += d * d;
         }
         mean[(size_t)m * n_out + o] = mu;
@@ -282,10 +284,11 @@ hipError_t launch_loss_finish(const float* part, long long s_part, int n_part, f
     return hipGetLastError();
 }
 
-hipError_t launch_ensemble(const float* y, long long s_net, int ld, int B, int n_out, int nets, float* mean,
-                           float* spread, hipStream_t s)
+hipError_t launch_ensemble(const float* y, long long s_net, int ld, int B, int n_out, int nets, const float* oshift,
+                           const float* oscale, float* mean, float* spread, hipStream_t s)
 {
-    hipLaunchKernelGGL(ensemble, dim3((B + 255) / 256), dim3(256), 0, s, y, s_net, ld, B, n_out, nets, mean, spread);
+    hipLaunchKernelGGL(ensemble, dim3((B + 255) / 256), dim3(256), 0, s, y, s_net, ld, B, n_out, nets, oshift, oscale,
+                       mean, spread);
     return hipGetLastError();
 }
 

@@ -1,0 +1,213 @@
+"""Paper-fidelity runs of the full model (Sec. II.D, III and IV) on the
+library: the full Gaussian-beam standing wave, the box co-moving with the
+electron and the gauge shift A_m, at the paper's parameters.
+
+Units: atomic units with hbar = m = 1, so the paper's m c is C_AU and its
+hbar k_L = 0.1 m c is k_L = 0.1 C_AU.  Parameters of the showcase (Sec. II.D):
+a 2048 x 128 grid over 80 lambda x 40 lambda, x in [-40, 40) lambda, the y
+window starting at [-160, -120) lambda and moving with v_y = c/sqrt2; packet
+at kinetic p0 = (-hbar k_L, m c), r0 = (140 lambda_C, -140 lambda),
+sigma_p = hbar k_L/200, spin +x; dt = 0.05 hbar/(m c^2) and the travel time
+280 lambda sqrt2 / c; omega = c k_L, A0 = 0.1 m c/q, eps = 0.02, A_m = m c.
+
+* ``showcase`` (E1): band and spin-resolved probabilities, and the
+  spin-resolved densities |c^+-(p)|^2 at the diffracted peak p = (hbar k_L,
+  m c) (the paper reports 4.6e-5 and 3.9e-3 there; its values are grid-point
+  densities of an unstated normalisation, so the comparison is the ratio).
+* ``scaling`` (E3): the spin-flip density at the diffracted peak over
+  eps in {0.01, 0.02, 0.05, 0.1} and hbar k_L/(m c) in {0.05, 0.07, 0.1};
+  the paper finds it proportional to (k_L/eps)^2.
+* ``longitudinal`` (E4): with and without A_x; the paper finds the
+  difference of |c^s|^2 proportional to eps^2, nearly independent of k_L.
+* ``diffraction`` (E5, E6): eps = 0.1, k_L = 0.1, A0 = 0.4 m c/q on
+  2048 x 256 at p_x = -hbar k_L and p_x = 0: the momentum of the peak of each
+  diffraction order against the energy-conservation estimate of Eq. 22,
+  Delta p_y = -2 n hbar k_L p_x/(m c) - 2 n^2 hbar^2 k_L^2/(m c).
+
+    python -m paper_2307_01571_amd.experiments showcase --out e1.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import qw
+from . import workloads as W
+
+C = W.C_AU
+
+
+def _log(*a):
+    print("[experiments]", *a, file=sys.stderr, flush=True)
+
+
+def setup(kl_mc=0.1, eps=0.02, a0_mc=0.1, nx=2048, ny=128, box_x=80, box_y=40, px_kl=-1.0, longitudinal=1):
+    """Grid, beam, packet, frame and step plan of the showcase family (lengths in lambda)."""
+    kl = kl_mc * C
+    lam = 2 * math.pi / kl
+    lam_c = 2 * math.pi / C
+    g = W.GridSpec(nx=nx, ny=ny, x_min=-box_x / 2 * lam, y_min=(-140 - box_y / 2) * lam, lx=box_x * lam,
+                   ly=box_y * lam)
+    b = W.BeamSpec(mode=qw.QW_BEAM_GAUSSIAN_FULL, a0=a0_mc * C, lambda_l=lam, w0=1.0 / (kl * eps), ramp_periods=0.0,
+                   longitudinal=longitudinal)
+    sigma_p = kl / 200
+    p = W.PacketSpec(p0x=px_kl * kl, p0y=C, x0=140 * lam_c, y0=-140 * lam, sigma_x=1 / (2 * sigma_p), spin=1)
+    dt = 0.05 / C ** 2
+    steps = int(round(280 * lam * math.sqrt(2) / C / dt))
+    half = box_x  # k_L / dk_x with dk_x = 2 pi / (box_x lambda)
+    o = W.ObsSpec(band_ref_idx=int(round(px_kl * half)), band_half_idx=half, window_idx=half // 2, n_max=3, spin0=1)
+    return dict(grid=g, beam=b, packet=p, obs=o, vy=C / math.sqrt(2), a_m=C, dt=dt, steps=steps, kl=kl, lam=lam)
+
+
+def run(cfg, prec=qw.QW_F64, chunk=50_000):
+    """Propagate to the end; returns observables, momentum maps and timing."""
+    sim = qw.Sim(cfg["grid"], prec, beam=cfg["beam"])
+    sim.set_frame(cfg["vy"], cfg["a_m"])
+    sim.init_packet(cfg["packet"])
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < cfg["steps"]:
+        n = min(chunk, cfg["steps"] - done)
+        sim.step(n, done * cfg["dt"], cfg["dt"])
+        done += n
+        torch.cuda.synchronize()
+        _log(f"  {done}/{cfg['steps']} steps, {time.perf_counter() - t0:.1f} s")
+    el = time.perf_counter() - t0
+    obs = qw.unpack_observables(sim.observables(cfg["obs"]), cfg["obs"].n_max)
+    maps = sim.momentum_maps()
+    sim.close()
+    return obs, maps, el
+
+
+def momenta(cfg):
+    g = cfg["grid"]
+    px = 2 * math.pi * np.fft.fftfreq(g.nx, d=g.lx / g.nx)
+    py = 2 * math.pi * np.fft.fftfreq(g.ny, d=g.ly / g.ny) + cfg["a_m"]  # kinetic
+    return px, py
+
+
+def peak_near(cfg, maps, px_target, py_target, col=0, radius=(3, 6)):
+    """Largest value of maps[..., col] within a few cells of (px, py) (kinetic)."""
+    px, py = momenta(cfg)
+    ix = int(np.argmin(np.abs(px - px_target)))
+    iy = int(np.argmin(np.abs(py - py_target)))
+    best, at = -1.0, (iy, ix)
+    for dy in range(-radius[1], radius[1] + 1):
+        for dx in range(-radius[0], radius[0] + 1):
+            j, i = (iy + dy) % len(py), (ix + dx) % len(px)
+            if maps[j, i, col] > best:
+                best, at = maps[j, i, col], (j, i)
+    return float(best), float(px[at[1]]), float(py[at[0]])
+
+
+def showcase(prec=qw.QW_F64, **kw):
+    cfg = setup(**kw)
+    _log(f"showcase: {cfg['grid'].nx}x{cfg['grid'].ny}, {cfg['steps']} steps")
+    obs, maps, el = run(cfg, prec)
+    total = float(np.sum(maps[..., 0]))
+    # the diffracted peak p = (+hbar k_L, m c); normalise densities to the total
+    cp, cpx, cpy = peak_near(cfg, maps, cfg["kl"], C, col=1)
+    cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
+    c0p, _, _ = peak_near(cfg, maps, -cfg["kl"], C, col=1)
+    return {"config": {"kl_mc": cfg["kl"] / C, "grid": [cfg["grid"].nx, cfg["grid"].ny], "steps": cfg["steps"],
+                       "dt": cfg["dt"], "eps": 1 / (cfg["kl"] * cfg["beam"].w0), "a0": cfg["beam"].a0,
+                       "prec": "f64" if prec == qw.QW_F64 else "f32"},
+            "seconds": el, "cell_steps_per_s": cfg["grid"].nx * cfg["grid"].ny * cfg["steps"] / el,
+            "bands": {k: (list(map(float, v)) if isinstance(v, np.ndarray) else v) for k, v in obs.items()},
+            "peak_plus_k": {"c_plus_sq": cp / total, "c_minus_sq": cm / total, "ratio_minus_over_plus": cm / cp,
+                            "at": [cpx / cfg["kl"], cpy / C]},
+            "peak_minus_k_c_plus_sq": c0p / total}
+
+
+def scaling(prec=qw.QW_F32, eps_list=(0.01, 0.02, 0.05, 0.1), kl_list=(0.05, 0.07, 0.1), longitudinal_off=False):
+    rows = []
+    for kl in kl_list:
+        for eps in eps_list:
+            for lon in ((1, 0) if longitudinal_off else (1,)):
+                cfg = setup(kl_mc=kl, eps=eps, longitudinal=lon)
+                _log(f"scaling: k_L = {kl} m c, eps = {eps}, A_x {'on' if lon else 'off'}, {cfg['steps']} steps")
+                obs, maps, el = run(cfg, prec)
+                total = float(np.sum(maps[..., 0]))
+                cp, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=1)
+                cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
+                rows.append({"kl_mc": kl, "eps": eps, "longitudinal": lon, "steps": cfg["steps"], "seconds": el,
+                             "c_plus_sq": cp / total, "c_minus_sq": cm / total,
+                             "P_plus1": float(obs["P"][cfg["obs"].n_max + 1]),
+                             "P_plus1_flip": float(obs["Pm"][cfg["obs"].n_max + 1]), "P_flip": obs["P_flip"]})
+    return rows
+
+
+def loglog_slope(x, y):
+    x, y = np.log(np.asarray(x, float)), np.log(np.asarray(y, float))
+    return float(np.polyfit(x, y, 1)[0])
+
+
+def diffraction(prec=qw.QW_F64, px_kl=-1.0, n_orders=(-3, -2, -1, 0, 1, 2, 3)):
+    cfg = setup(kl_mc=0.1, eps=0.1, a0_mc=0.4, ny=256, px_kl=px_kl)
+    _log(f"diffraction: p_x = {px_kl} hbar k_L, {cfg['steps']} steps")
+    obs, maps, el = run(cfg, prec)
+    px, py = momenta(cfg)
+    kl = cfg["kl"]
+    total = float(np.sum(maps[..., 0]))
+    rows = []
+    for n in n_orders:
+        pxn = px_kl * kl + 2 * n * kl
+        ix = int(np.argmin(np.abs(px - pxn)))
+        col = maps[:, ix, 0]
+        j = int(np.argmax(col))
+        dpy = float(py[j] - C)
+        est = -2 * n * kl * (px_kl * kl) / C - 2 * n * n * kl * kl / C
+        rows.append({"n": n, "peak_density": float(col[j]) / total, "dpy_measured": dpy, "dpy_eq22": est,
+                     "dpy_cell": float(2 * math.pi / cfg["grid"].ly),
+                     "c_plus_sq": float(maps[j, ix, 1]) / total, "c_minus_sq": float(maps[j, ix, 2]) / total})
+    return {"px_kl": px_kl, "seconds": el, "orders": rows,
+            "bands": {k: (list(map(float, v)) if isinstance(v, np.ndarray) else v) for k, v in obs.items()}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction"])
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    qw.lib()
+    prec = qw.QW_F64 if a.prec == "f64" else qw.QW_F32
+    if a.what == "showcase":
+        res = showcase(prec)
+    elif a.what == "scaling":
+        rows = scaling(prec)
+        res = {"rows": rows}
+        for kl in sorted({r["kl_mc"] for r in rows}):
+            sel = [r for r in rows if r["kl_mc"] == kl]
+            res[f"slope_vs_eps_kl{kl}"] = loglog_slope([r["eps"] for r in sel], [r["c_minus_sq"] for r in sel])
+        for eps in sorted({r["eps"] for r in rows}):
+            sel = [r for r in rows if r["eps"] == eps]
+            res[f"slope_vs_kl_eps{eps}"] = loglog_slope([r["kl_mc"] for r in sel], [r["c_minus_sq"] for r in sel])
+    elif a.what == "longitudinal":
+        rows = scaling(prec, longitudinal_off=True)
+        res = {"rows": rows}
+        for kl in sorted({r["kl_mc"] for r in rows}):
+            d = []
+            for eps in sorted({r["eps"] for r in rows}):
+                on = [r for r in rows if r["kl_mc"] == kl and r["eps"] == eps and r["longitudinal"] == 1][0]
+                off = [r for r in rows if r["kl_mc"] == kl and r["eps"] == eps and r["longitudinal"] == 0][0]
+                d.append((eps, abs(off["c_minus_sq"] - on["c_minus_sq"]), abs(off["c_plus_sq"] - on["c_plus_sq"])))
+            res[f"diff_kl{kl}"] = d
+            res[f"slope_minus_kl{kl}"] = loglog_slope([x[0] for x in d], [x[1] for x in d])
+            res[f"slope_plus_kl{kl}"] = loglog_slope([x[0] for x in d], [x[2] for x in d])
+    else:
+        res = {"E5": diffraction(prec, px_kl=-1.0), "E6": diffraction(prec, px_kl=0.0)}
+    with open(a.out, "w") as f:
+        json.dump(res, f, indent=1)
+    _log(json.dumps(res)[:2000])
+
+
+if __name__ == "__main__":
+    main()

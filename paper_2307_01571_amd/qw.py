@@ -31,15 +31,16 @@ QW_F32 = 1
 QW_BEAM_NONE = 0
 QW_BEAM_STANDING_PARAXIAL = 1
 QW_BEAM_UNIFORM = 2
+QW_BEAM_GAUSSIAN_FULL = 3
 
-EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_init_packet", "qw_step_n",
-            "qw_observables", "qw_kernel_timing", "qw_kernel_times", "qw_last_error", "qw_destroy",
+EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_set_frame", "qw_init_packet", "qw_step_n",
+            "qw_observables", "qw_momentum_maps", "qw_kernel_timing", "qw_kernel_times", "qw_last_error", "qw_destroy",
             "qw_batch_layout", "qw_batch_init", "qw_batch_init_packets", "qw_batch_step_n",
             "qw_batch_observables", "qw_batch_schedule", "qw_batch_set_schedule", "qw_batch_set_launch",
             "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
             "qw_batch_destroy",
             "qw_mlp_param_count", "qw_mlp_workspace_bytes", "qw_mlp_init", "qw_mlp_set_params",
-            "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_gradients", "qw_mlp_train_step",
+            "qw_mlp_set_output_map", "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_gradients", "qw_mlp_train_step",
             "qw_gemm_bf16_nt", "qw_mlp_last_error", "qw_mlp_destroy")
 _NO_STATUS = ("qw_last_error", "qw_destroy", "qw_batch_last_error", "qw_batch_destroy", "qw_mlp_last_error",
               "qw_mlp_destroy")
@@ -56,6 +57,10 @@ class qw_beam(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("a0", ctypes.c_double), ("lambda_l", ctypes.c_double),
                 ("w0", ctypes.c_double), ("ramp_periods", ctypes.c_double),
                 ("longitudinal", ctypes.c_int32), ("ux", ctypes.c_double), ("uy", ctypes.c_double)]
+
+
+class qw_frame(ctypes.Structure):
+    _fields_ = [("vy", ctypes.c_double), ("a_m", ctypes.c_double)]
 
 
 class qw_packet(ctypes.Structure):
@@ -97,9 +102,11 @@ def lib():
     L.qw_workspace_bytes.argtypes = [ctypes.POINTER(qw_grid), ctypes.POINTER(ctypes.c_size_t)]
     L.qw_init_grid.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(qw_grid), vp, ctypes.c_size_t, vp]
     L.qw_set_beam.argtypes = [vp, ctypes.POINTER(qw_beam)]
+    L.qw_set_frame.argtypes = [vp, ctypes.POINTER(qw_frame)]
     L.qw_init_packet.argtypes = [vp, vp, ctypes.POINTER(qw_packet), vp]
     L.qw_step_n.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, vp]
     L.qw_observables.argtypes = [vp, vp, ctypes.POINTER(qw_obs_spec), dp, ctypes.c_int32, vp]
+    L.qw_momentum_maps.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     L.qw_kernel_timing.argtypes = [vp, ctypes.c_int]
     L.qw_kernel_times.argtypes = [vp, dp, ctypes.c_int32, vp]
     L.qw_last_error.argtypes = [vp]
@@ -131,6 +138,7 @@ def lib():
     L.qw_mlp_init.argtypes = [ctypes.POINTER(vp), shp, fp, fp, vp, ctypes.c_size_t, vp]
     L.qw_mlp_set_params.argtypes = [vp, vp, vp]
     L.qw_mlp_get_params.argtypes = [vp, vp, vp]
+    L.qw_mlp_set_output_map.argtypes = [vp, fp, fp, vp]
     L.qw_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     L.qw_mlp_predict.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.qw_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp]
@@ -177,6 +185,10 @@ def qw_set_beam(ctx: int, beam: qw_beam) -> None:
     _check(lib().qw_set_beam(ctypes.c_void_p(ctx), ctypes.byref(beam)), ctx)
 
 
+def qw_set_frame(ctx: int, frame: qw_frame) -> None:
+    _check(lib().qw_set_frame(ctypes.c_void_p(ctx), ctypes.byref(frame)), ctx)
+
+
 def qw_init_packet(ctx: int, psi_ptr: int, packet: qw_packet, stream: int) -> None:
     _check(lib().qw_init_packet(ctypes.c_void_p(ctx), ctypes.c_void_p(psi_ptr), ctypes.byref(packet),
                                 ctypes.c_void_p(stream)), ctx)
@@ -195,6 +207,11 @@ def qw_observables(ctx: int, psi_ptr: int, spec: qw_obs_spec, stream: int, check
     if check:
         _check(rc, ctx)
     return rc, [float(v) for v in out]
+
+
+def qw_momentum_maps(ctx: int, psi_ptr: int, out_ptr: int, out_len: int, stream: int) -> None:
+    _check(lib().qw_momentum_maps(ctypes.c_void_p(ctx), ctypes.c_void_p(psi_ptr), ctypes.c_void_p(out_ptr),
+                                  int(out_len), ctypes.c_void_p(stream)), ctx)
 
 
 def qw_kernel_timing(ctx: int, enable: bool) -> None:
@@ -352,6 +369,12 @@ def qw_mlp_set_params(h: int, params_ptr: int, stream: int) -> None:
     _mcheck(lib().qw_mlp_set_params(_p(h), _p(params_ptr), _p(stream)), h)
 
 
+def qw_mlp_set_output_map(h: int, shift, scale, n_out: int, stream: int) -> None:
+    sh = (ctypes.c_float * n_out)(*[float(v) for v in shift])
+    sc = (ctypes.c_float * n_out)(*[float(v) for v in scale])
+    _mcheck(lib().qw_mlp_set_output_map(_p(h), sh, sc, _p(stream)), h)
+
+
 def qw_mlp_get_params(h: int, params_ptr: int, stream: int) -> None:
     _mcheck(lib().qw_mlp_get_params(_p(h), _p(params_ptr), _p(stream)), h)
 
@@ -421,6 +444,9 @@ class Sim:
     def set_beam(self, b) -> None:
         qw_set_beam(self.ctx, qw_beam(b.mode, b.a0, b.lambda_l, b.w0, b.ramp_periods, b.longitudinal, b.ux, b.uy))
 
+    def set_frame(self, vy: float = 0.0, a_m: float = 0.0) -> None:
+        qw_set_frame(self.ctx, qw_frame(vy, a_m))
+
     def init_packet(self, p) -> None:
         qw_init_packet(self.ctx, self.psi.data_ptr(),
                        qw_packet(p.p0x, p.p0y, p.x0, p.y0, p.sigma_x, p.spin), self.stream())
@@ -437,6 +463,13 @@ class Sim:
         spec = qw_obs_spec(o.band_ref_idx, o.band_half_idx, o.window_idx, o.n_max, o.spin0)
         rc, out = qw_observables(self.ctx, self.psi.data_ptr(), spec, self.stream(), check=check)
         return out if check else (rc, out)
+
+    def momentum_maps(self):
+        """(|phi|^2, |c+|^2, |c-|^2) per momentum cell as a (ny, nx, 3) numpy array, transform order."""
+        out = self.torch.empty((self.g.ny, self.g.nx, 3), dtype=self.torch.float64, device=self.device)
+        qw_momentum_maps(self.ctx, self.psi.data_ptr(), out.data_ptr(), out.numel(), self.stream())
+        self.torch.cuda.synchronize(self.device)
+        return out.cpu().numpy()
 
     def state(self):
         """Host copy of psi as a numpy complex128 array."""
@@ -575,6 +608,9 @@ class MLP:
         assert p.numel() == self.shape.n_nets * self.per_net
         qw_mlp_set_params(self.h, p.data_ptr(), self.stream())
         self.torch.cuda.synchronize(self.device)
+
+    def set_output_map(self, shift, scale) -> None:
+        qw_mlp_set_output_map(self.h, shift, scale, self.shape.n_out, self.stream())
 
     def params(self):
         out = self.torch.empty(self.shape.n_nets * self.per_net, dtype=self.torch.float32, device=self.device)

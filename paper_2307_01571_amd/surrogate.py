@@ -121,16 +121,31 @@ def make_net(max_batch: int = 4096, seed: int = 0):
     return net
 
 
+def target_map(y):
+    """Per-output (mean, standard deviation) of the training targets; the
+    network learns the standardised targets and predicts through the map."""
+    y = np.asarray(y, dtype=np.float64)
+    mu = y.mean(axis=0)
+    sd = y.std(axis=0)
+    sd = np.where(sd > 0, sd, 1.0)
+    return mu, sd
+
+
 def train(x, y, epochs: int = 200, batch: int = 4096, lr: float = 1e-3, lr_end: float = 1e-5, seed: int = 0,
           net=None):
-    """Adam on shuffled minibatches; returns the net and the loss history (per epoch, mean over nets)."""
+    """Adam on shuffled minibatches of standardised targets; returns the net
+    (predicting in the targets' units) and the loss history (per epoch, mean
+    over nets, in standardised units)."""
     import torch
     dev = torch.device("cuda")
+    mu, sd = target_map(y)
     xd = torch.as_tensor(x, dtype=torch.float32, device=dev)
-    yd = torch.as_tensor(y, dtype=torch.float32, device=dev)
+    yd = torch.as_tensor((np.asarray(y) - mu) / sd, dtype=torch.float32, device=dev)
     n = xd.shape[0]
     batch = min(batch, n)
     net = net or make_net(max_batch=max(batch, 4096), seed=seed)
+    net.set_output_map(mu, sd)
+    net.target_mean, net.target_std = mu, sd
     g = torch.Generator(device="cpu").manual_seed(seed)
     loss = torch.zeros(W.SURROGATE_SHAPE["n_nets"], device=dev)
     per_epoch = n // batch
@@ -183,11 +198,23 @@ class SurrogateWithFallback:
 
 
 def evaluate(net, x, y, tol: float = 1e-2) -> dict:
+    """Errors of the ensemble mean against the solver.  Besides absolute
+    errors (the fallback tolerance is absolute), each output's RMS error is
+    given relative to its spread over the evaluated set and to the RMS error
+    of the constant predictor (the training mean): skill = 1 - (rmse /
+    rmse_constant)^2."""
     mean, spread = predict(net, x)
     err = np.abs(mean - y)
     worst = err.max(axis=1)
     accept = spread <= tol
-    res = {"samples": int(len(x)), "mae": err.mean(axis=0).tolist(), "max_abs": err.max(axis=0).tolist(),
+    rmse = np.sqrt(np.mean((mean - y) ** 2, axis=0))
+    mu = getattr(net, "target_mean", np.mean(y, axis=0))
+    rmse0 = np.sqrt(np.mean((mu - y) ** 2, axis=0))
+    res = {"samples": int(len(x)), "outputs": list(W.SURROGATE_OUTPUTS),
+           "rmse": rmse.tolist(), "rmse_over_std": (rmse / np.maximum(np.std(y, axis=0), 1e-300)).tolist(),
+           "skill_vs_constant": (1 - (rmse / np.maximum(rmse0, 1e-300)) ** 2).tolist(),
+           "mae": err.mean(axis=0).tolist(), "max_abs": err.max(axis=0).tolist(),
+           "max_abs_rel_to_output_max": (err.max(axis=0) / np.maximum(np.abs(y).max(axis=0), 1e-300)).tolist(),
            "max_abs_all": float(worst.max()), "share_within_tol": float(np.mean(worst <= tol)),
            "fallback_share": float(1 - accept.mean()),
            "max_abs_accepted": float(worst[accept].max()) if accept.any() else None,

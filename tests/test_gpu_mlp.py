@@ -159,10 +159,14 @@ def test_predict_is_the_ensemble_mean_and_spread():
     print_case(test="mlp_predict")
     net, params, x, t, shift, scale = make_net(n_nets=4)
     y = net.forward(torch.from_numpy(x)).double().cpu().numpy()
+    osh = np.array([0.5, -1.0, 2.0, 0.0, 1e-3, 3.0], dtype=np.float32).astype(np.float64)
+    osc = np.array([2.0, 0.5, 1e-4, 1.0, 3.0, 0.25], dtype=np.float32).astype(np.float64)
+    net.set_output_map(osh, osc)
+    y = y * osc + osh
     mean, spread = net.predict(torch.from_numpy(x))
     mean, spread = mean.double().cpu().numpy(), spread.double().cpu().numpy()
-    assert np.max(np.abs(mean - y.mean(axis=0))) <= 1e-6
-    assert np.max(np.abs(spread - y.std(axis=0, ddof=1).max(axis=1))) <= 1e-5
+    assert np.max(np.abs(mean - y.mean(axis=0))) <= 1e-6 * np.max(np.abs(y))
+    assert np.max(np.abs(spread - y.std(axis=0, ddof=1).max(axis=1))) <= 1e-5 * np.max(np.abs(y))
     net.close()
 
 

@@ -50,10 +50,12 @@ def test_trained_surrogate_with_fallback():
     x, y, rid = S.generate(64, seed=3, steps=2000, snap_every=200, n=512)
     held = rid >= 56
     net, hist = S.train(x[~held], y[~held], epochs=300, batch=256, lr=2e-3)
-    assert hist[-1] < 0.1 * hist[0]
+    assert hist[-1] < 0.5 * hist[0]  # standardised units: 1 = the constant predictor
     ev = S.evaluate(net, x[held], y[held])
     print("  held-out:", ev)
     assert ev["max_abs_all"] < 0.2
+    # better than the constant predictor on the leading outputs
+    assert ev["skill_vs_constant"][0] > 0.5 and ev["skill_vs_constant"][1] > 0.5
     pol = S.SurrogateWithFallback(net, tol=1e-2)
     # queries inside and far outside the training ranges (A0 = 3 was never seen)
     q = np.concatenate([x[held][:6], x[held][:2] * np.array([1, 0, 1, 1, 1]) + np.array([0, 3.0, 0, 0, 0])])
