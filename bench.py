@@ -156,6 +156,57 @@ def batch_section(qw, W, torch, steps, single_steps):
             "schedules": chosen, "launch": launches}
 
 
+def learned_section(qw, W, torch, batch=4096, reps=50):
+    """Surrogate network (4 nets, 5 -> 4 x 256 GELU -> 6) on the matrix cores:
+    one training step (forward, back-propagation, Adam) on a batch of 4096 and
+    ensemble predictions of 1 and 4096 queries.  The products of a training
+    step total 3 x 2 x (5 + 3 x 256 + 6) x 256 x batch x nets flops (forward,
+    input gradient, weight gradient; the first layer's input gradient is not
+    formed); the MFMA roofline is the dense BF16 peak."""
+    import numpy as np
+    s = W.SURROGATE_SHAPE
+    shift, scale = W.surrogate_input_map()
+    net = qw.MLP(s["n_in"], s["width"], s["depth"], s["n_out"], s["n_nets"], max_batch=batch, shift=shift,
+                 scale=scale)
+    net.set_params(torch.from_numpy(np.concatenate(
+        [W.mlp_init_params(k, s["n_in"], s["width"], s["depth"], s["n_out"]) for k in range(s["n_nets"])])))
+    rng = np.random.default_rng(0)
+    lo = np.array([r[0] for r in W.SURROGATE_INPUT_RANGES])
+    hi = np.array([r[1] for r in W.SURROGATE_INPUT_RANGES])
+    x = torch.as_tensor(lo + (hi - lo) * rng.random((batch, 5)), dtype=torch.float32, device="cuda")
+    t = torch.as_tensor(rng.standard_normal((batch, 6)), dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / reps
+    w, d = s["width"], s["depth"]
+    macs = (s["n_in"] * w + (d - 1) * w * w + w * s["n_out"]) * batch * s["n_nets"]
+    flops = 2 * macs * 3 - 2 * s["n_in"] * w * batch * s["n_nets"]
+    lat = {}
+    for q in (1, batch):
+        xq = x[:q].contiguous()
+        for _ in range(5):
+            net.predict(xq)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            m, _ = net.predict(xq)
+        torch.cuda.synchronize()
+        lat[str(q)] = (time.perf_counter() - t0) / reps
+    net.close()
+    log(f"learned: train step {step_s * 1e6:.1f} us ({flops / step_s / 1e12:.1f} TFLOP/s); "
+        f"predict 1: {lat['1'] * 1e6:.1f} us, {batch}: {lat[str(batch)] * 1e6:.1f} us")
+    return {"train_step_us": step_s * 1e6, "batch": batch, "nets": s["n_nets"], "train_step_flops": flops,
+            "roofline": {"bound": "mfma", "achieved": round(flops / step_s / 1e12, 2), "peak": 2500.0,
+                         "unit": "TFLOP/s", "frac": flops / step_s / 1e12 / 2500.0,
+                         "note": "22 small launches per step: latency-bound, not MFMA-bound"},
+            "predict_us": {k: v * 1e6 for k, v in lat.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +219,7 @@ def main():
                     help="steps of the batching workload (96 instances) to time; 0 skips it")
     ap.add_argument("--batch-single-steps", type=int, default=500,
                     help="steps per instance when the same instances run one by one")
+    ap.add_argument("--no-learned", action="store_true", help="skip the surrogate network timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
                          "128 MiB written), the reference for bandwidth and traffic counters")
@@ -258,6 +310,8 @@ def main():
 
     if a.batch_steps > 0:
         extra["batch"] = batch_section(qw, W, torch, a.batch_steps, a.batch_single_steps)
+    if not a.no_learned:
+        extra["learned"] = learned_section(qw, W, torch)
 
     # oracle on a bounded sample: the same grid and field, a few steps
     import oracle
