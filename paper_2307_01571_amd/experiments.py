@@ -86,6 +86,44 @@ def run(cfg, prec=qw.QW_F64, chunk=50_000):
     return obs, maps, el
 
 
+def run_many(cfgs, prec=qw.QW_F64, chunk=20_000):
+    """Several runs at once, each on its own stream (default priority): one
+    2048 x 128 run fills about half the GPU, so concurrent runs overlap.
+    Returns [(observables, momentum maps, seconds of the whole group)]."""
+    import torch
+    sims, streams = [], []
+    for cfg in cfgs:
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            sim = qw.Sim(cfg["grid"], prec, beam=cfg["beam"])
+            sim.set_frame(cfg["vy"], cfg["a_m"])
+            sim.init_packet(cfg["packet"])
+        sims.append(sim)
+        streams.append(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = [0] * len(cfgs)
+    while any(d < c["steps"] for d, c in zip(done, cfgs)):
+        for i, (sim, st, cfg) in enumerate(zip(sims, streams, cfgs)):
+            if done[i] >= cfg["steps"]:
+                continue
+            n = min(chunk, cfg["steps"] - done[i])
+            with torch.cuda.stream(st):
+                sim.step(n, done[i] * cfg["dt"], cfg["dt"])
+            done[i] += n
+        torch.cuda.synchronize()
+        _log(f"  {min(done)}..{max(done)} steps of {len(cfgs)} runs, {time.perf_counter() - t0:.1f} s")
+    el = time.perf_counter() - t0
+    out = []
+    for sim, st, cfg in zip(sims, streams, cfgs):
+        with torch.cuda.stream(st):
+            obs = qw.unpack_observables(sim.observables(cfg["obs"]), cfg["obs"].n_max)
+            maps = sim.momentum_maps()
+        sim.close()
+        out.append((obs, maps, el))
+    return out
+
+
 def momenta(cfg):
     g = cfg["grid"]
     px = 2 * math.pi * np.fft.fftfreq(g.nx, d=g.lx / g.nx)
@@ -127,20 +165,24 @@ def showcase(prec=qw.QW_F64, **kw):
 
 
 def scaling(prec=qw.QW_F32, eps_list=(0.01, 0.02, 0.05, 0.1), kl_list=(0.05, 0.07, 0.1), longitudinal_off=False):
+    """The scan's runs of one k_L go together (equal step counts)."""
     rows = []
     for kl in kl_list:
+        cfgs, keys = [], []
         for eps in eps_list:
             for lon in ((1, 0) if longitudinal_off else (1,)):
-                cfg = setup(kl_mc=kl, eps=eps, longitudinal=lon)
-                _log(f"scaling: k_L = {kl} m c, eps = {eps}, A_x {'on' if lon else 'off'}, {cfg['steps']} steps")
-                obs, maps, el = run(cfg, prec)
-                total = float(np.sum(maps[..., 0]))
-                cp, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=1)
-                cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
-                rows.append({"kl_mc": kl, "eps": eps, "longitudinal": lon, "steps": cfg["steps"], "seconds": el,
-                             "c_plus_sq": cp / total, "c_minus_sq": cm / total,
-                             "P_plus1": float(obs["P"][cfg["obs"].n_max + 1]),
-                             "P_plus1_flip": float(obs["Pm"][cfg["obs"].n_max + 1]), "P_flip": obs["P_flip"]})
+                cfgs.append(setup(kl_mc=kl, eps=eps, longitudinal=lon))
+                keys.append((eps, lon))
+        _log(f"scaling: k_L = {kl} m c, {len(cfgs)} runs of {cfgs[0]['steps']} steps")
+        for (eps, lon), cfg, (obs, maps, el) in zip(keys, cfgs, run_many(cfgs, prec)):
+            total = float(np.sum(maps[..., 0]))
+            cp, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=1)
+            cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
+            rows.append({"kl_mc": kl, "eps": eps, "longitudinal": lon, "steps": cfg["steps"], "group_seconds": el,
+                         "c_plus_sq": cp / total, "c_minus_sq": cm / total,
+                         "P_plus1": float(obs["P"][cfg["obs"].n_max + 1]),
+                         "P_plus1_plus": float(obs["Pp"][cfg["obs"].n_max + 1]),
+                         "P_plus1_flip": float(obs["Pm"][cfg["obs"].n_max + 1]), "P_flip": obs["P_flip"]})
     return rows
 
 
@@ -157,6 +199,8 @@ def diffraction(prec=qw.QW_F64, px_kl=-1.0, n_orders=(-3, -2, -1, 0, 1, 2, 3)):
     kl = cfg["kl"]
     total = float(np.sum(maps[..., 0]))
     rows = []
+    o = cfg["obs"]
+    dkx = 2 * math.pi / cfg["grid"].lx
     for n in n_orders:
         pxn = px_kl * kl + 2 * n * kl
         ix = int(np.argmin(np.abs(px - pxn)))
@@ -164,8 +208,15 @@ def diffraction(prec=qw.QW_F64, px_kl=-1.0, n_orders=(-3, -2, -1, 0, 1, 2, 3)):
         j = int(np.argmax(col))
         dpy = float(py[j] - C)
         est = -2 * n * kl * (px_kl * kl) / C - 2 * n * n * kl * kl / C
-        rows.append({"n": n, "peak_density": float(col[j]) / total, "dpy_measured": dpy, "dpy_eq22": est,
-                     "dpy_cell": float(2 * math.pi / cfg["grid"].ly),
+        # the largest density anywhere in the order's window of columns
+        cols = np.nonzero(np.abs(np.rint((px - pxn) / dkx)) <= o.window_idx)[0]
+        sub = maps[:, cols, 0]
+        jj, ii = np.unravel_index(int(np.argmax(sub)), sub.shape)
+        pop = float(obs["P"][o.n_max + n]) if abs(n) <= o.n_max else None
+        rows.append({"n": n, "band_P": pop, "peak_density": float(col[j]) / total, "dpy_measured": dpy,
+                     "dpy_eq22": est, "dpy_cell": float(2 * math.pi / cfg["grid"].ly),
+                     "window_peak_density": float(sub[jj, ii]) / total,
+                     "window_peak_at": [float(px[cols[ii]] / kl), float((py[jj] - C) / kl)],
                      "c_plus_sq": float(maps[j, ix, 1]) / total, "c_minus_sq": float(maps[j, ix, 2]) / total})
     return {"px_kl": px_kl, "seconds": el, "orders": rows,
             "bands": {k: (list(map(float, v)) if isinstance(v, np.ndarray) else v) for k, v in obs.items()}}
@@ -176,22 +227,25 @@ def main(argv=None):
     ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction"])
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--kl", type=float, nargs="+", default=[0.05, 0.07, 0.1], help="hbar k_L / (m c) of the scans")
     a = ap.parse_args(argv)
     qw.lib()
     prec = qw.QW_F64 if a.prec == "f64" else qw.QW_F32
     if a.what == "showcase":
         res = showcase(prec)
     elif a.what == "scaling":
-        rows = scaling(prec)
+        rows = scaling(prec, kl_list=a.kl)
         res = {"rows": rows}
         for kl in sorted({r["kl_mc"] for r in rows}):
             sel = [r for r in rows if r["kl_mc"] == kl]
             res[f"slope_vs_eps_kl{kl}"] = loglog_slope([r["eps"] for r in sel], [r["c_minus_sq"] for r in sel])
         for eps in sorted({r["eps"] for r in rows}):
             sel = [r for r in rows if r["eps"] == eps]
-            res[f"slope_vs_kl_eps{eps}"] = loglog_slope([r["kl_mc"] for r in sel], [r["c_minus_sq"] for r in sel])
+            if len(sel) > 1:
+                res[f"slope_vs_kl_eps{eps}"] = loglog_slope([r["kl_mc"] for r in sel],
+                                                            [r["c_minus_sq"] for r in sel])
     elif a.what == "longitudinal":
-        rows = scaling(prec, longitudinal_off=True)
+        rows = scaling(prec, kl_list=a.kl, longitudinal_off=True)
         res = {"rows": rows}
         for kl in sorted({r["kl_mc"] for r in rows}):
             d = []
