@@ -12,6 +12,8 @@ HBM.  Afterwards, untimed:
     each pass and its fraction of the HBM roofline;
   * the batching workload (96 uneven instances, autotuned): batched and
     one-by-one rates and their ratio;
+  * the same step written with torch.fft (rocFFT) and torch elementwise
+    ops, and the bare library transforms alone, for comparison;
   * the oracle (FP64 CPU) on a bounded sample of the same workload.
 Prints one JSON line on stdout; progress goes to stderr.
 
@@ -28,24 +30,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4  # wave64 VALU issue: CUs x SIMDs x GHz / cycles per instruction
 BYTES_PER_CELL_PASS = {"f32": 64, "f64": 128}  # read + write of 4 complex per pass
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_2048sq_f32.json")
 
 
+HOST_ONLY_SOURCES = ("qw_api.cpp", "qw_batch.cpp", "qw_mlp.cpp", "qw_host.hpp")
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP library sources; measured traffic is reported only for the sources it was taken on."""
+    """Hash of the sources that define the kernels and their launch shapes.
+
+    Measured traffic is reported only for the kernels it was taken on; the
+    host-only files (argument checks, contexts, timing) are left out.
+    """
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2307_01571_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".inl", ".hpp", ".cpp")):
+        if name.endswith((".hip", ".inl", ".hpp")) and name not in HOST_ONLY_SOURCES:
             with open(os.path.join(csrc, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if still current."""
+def measured_counters(kernel: str):
+    """Counter figures per launch from the committed rocprofv3 runs, if still current.
+
+    Returns {"bytes": HBM read + write bytes, "valu_insts": wave-level VALU
+    instructions (None if not recorded)} or None when the kernel sources have
+    changed since the counters were taken.
+    """
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -54,7 +69,9 @@ def measured_traffic(kernel: str):
     if rec.get("source_sha256") != kernel_source_hash():
         return None
     k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k["read_bytes"] + k["write_bytes"]
+    if k is None:
+        return None
+    return {"bytes": k["read_bytes"] + k["write_bytes"], "valu_insts": k.get("valu_insts")}
 
 
 def log(*a):
@@ -207,6 +224,110 @@ def learned_section(qw, W, torch, batch=4096, reps=50):
             "predict_us": {k: v * 1e6 for k, v in lat.items()}}
 
 
+def unfused_section(qw, wl, torch, steps=100):
+    """The same Strang step written with torch.fft (rocFFT) and torch elementwise ops.
+
+    A timing comparison for the fused kernels, not part of the library: per
+    step fft2 -> K(dt) -> ifft2 -> V(t, dt) on the (ny, nx, 4) complex64
+    state, with the time-independent K coefficients precomputed (in FP64,
+    stored FP32) and V recomputed per step from the paraxial standing wave.
+    Also times the bare transforms (fft2 + ifft2, no pointwise work): the
+    floor of any design built on a library FFT.  The result after 20 steps
+    is checked against the library (relative L2 of the state).
+    """
+    g, b = wl.grid, wl.beam
+    dev = torch.device("cuda")
+    nx, ny, c, dt = g.nx, g.ny, g.c, wl.dt
+    f64 = torch.float64
+    x = g.x_min + (g.lx / nx) * torch.arange(nx, dtype=f64, device=dev)
+    y = g.y_min + (g.ly / ny) * torch.arange(ny, dtype=f64, device=dev)
+    kl = 2.0 * math.pi / b.lambda_l
+    omega = c * kl
+    t_ramp = b.ramp_periods * b.lambda_l / c
+    env = torch.exp(-(y / b.w0) ** 2)[:, None]
+    ay0 = (b.a0 * env * torch.cos(kl * x)[None, :]).float()
+    ax0 = (b.a0 * env * (2.0 * y / (kl * b.w0 ** 2))[:, None] * torch.sin(kl * x)[None, :]).float()
+    if not b.longitudinal:
+        ax0.zero_()
+    px = (2.0 * math.pi / g.lx) * torch.fft.fftfreq(nx, d=1.0 / nx, dtype=f64, device=dev)[None, :]
+    py = (2.0 * math.pi / g.ly) * torch.fft.fftfreq(ny, d=1.0 / ny, dtype=f64, device=dev)[:, None]
+    en = c * torch.sqrt(c * c + px * px + py * py)
+    kc = torch.cos(en * dt).float()
+    ks = (torch.sin(en * dt) / en).float()
+    pm = (c * torch.complex(px.expand(ny, nx), -py.expand(ny, nx))).to(torch.complex64)
+    pp = pm.conj()
+    cc = float(c * c)
+
+    def s_of(t):
+        f = math.sin(math.pi * t / (2.0 * t_ramp)) ** 2 if t < t_ramp else 1.0
+        return f * math.cos(omega * t)
+
+    def v_apply(psi, t, tau):
+        s = s_of(t)
+        ax, ay = s * ax0, s * ay0
+        am = torch.sqrt(ax * ax + ay * ay)
+        th = (c * tau) * am
+        cth = torch.cos(th)
+        sn = torch.where(am > 0, torch.sin(th) / torch.where(am > 0, am, torch.ones_like(am)),
+                         torch.full_like(am, c * tau))
+        m = torch.complex(ax, -ay)
+        p1, p2, p3, p4 = psi.unbind(-1)
+        ms = -1j * sn * m
+        msc = -1j * sn * m.conj()
+        return torch.stack((cth * p1 + ms * p4, cth * p2 + msc * p3, cth * p3 + ms * p2, cth * p4 + msc * p1), -1)
+
+    def k_apply(phi):
+        p1, p2, p3, p4 = phi.unbind(-1)
+        h = torch.stack((cc * p1 + pm * p4, cc * p2 + pp * p3, -cc * p3 + pm * p2, -cc * p4 + pp * p1), -1)
+        return kc[..., None] * phi - 1j * ks[..., None] * h
+
+    def body(psi, k):
+        phi = torch.fft.fft2(psi, dim=(0, 1))
+        psi = torch.fft.ifft2(k_apply(phi), dim=(0, 1))
+        return v_apply(psi, (k + 1) * dt, dt)
+
+    def run(psi, n):
+        psi = v_apply(psi, 0.0, 0.5 * dt)
+        for k in range(n):
+            phi = torch.fft.fft2(psi, dim=(0, 1))
+            psi = torch.fft.ifft2(k_apply(phi), dim=(0, 1))
+            psi = v_apply(psi, (k + 1) * dt, dt if k < n - 1 else 0.5 * dt)
+        return psi
+
+    sim = qw.Sim(g, qw.QW_F32, beam=b)
+    sim.init_packet(wl.packet)
+    psi0 = sim.psi.clone()
+    n_chk = 20
+    sim.step(n_chk, 0.0, dt)
+    ref = run(psi0, n_chk)
+    torch.cuda.synchronize()
+    rel = float(torch.linalg.vector_norm(ref - sim.psi) / torch.linalg.vector_norm(sim.psi))
+    sim.close()
+
+    psi = psi0.clone()
+    for k in range(5):
+        psi = body(psi, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        psi = body(psi, k)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / steps
+    for _ in range(3):
+        psi = torch.fft.ifft2(torch.fft.fft2(psi, dim=(0, 1)), dim=(0, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        psi = torch.fft.ifft2(torch.fft.fft2(psi, dim=(0, 1)), dim=(0, 1))
+    torch.cuda.synchronize()
+    fft_s = (time.perf_counter() - t0) / steps
+    log(f"unfused (torch.fft + elementwise): {step_s * 1e3:.3f} ms/step, bare fft2+ifft2 {fft_s * 1e3:.3f} ms; "
+        f"state vs library after {n_chk} steps: rel L2 {rel:.2e}")
+    return {"ms_per_step": step_s * 1e3, "fft_only_ms_per_step": fft_s * 1e3,
+            "rel_l2_vs_library_20_steps": rel, "steps_timed": steps,
+            "note": "torch.fft (rocFFT) + torch elementwise ops, same step; comparison only"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +341,8 @@ def main():
     ap.add_argument("--batch-single-steps", type=int, default=500,
                     help="steps per instance when the same instances run one by one")
     ap.add_argument("--no-learned", action="store_true", help="skip the surrogate network timing")
+    ap.add_argument("--no-unfused", action="store_true",
+                    help="skip the torch.fft (rocFFT) comparison of the same step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
                          "128 MiB written), the reference for bandwidth and traffic counters")
@@ -275,7 +398,8 @@ def main():
         log(f"  {k} pass: {cnt:.0f} launches, avg {avg_s * 1e6:.2f} us, {gbs:.0f} GB/s algorithmic")
     dom = max(per, key=lambda k: per[k]["avg_us"])
     dom_name = "col_pass" if dom == "col" else "row_pass"
-    traffic = measured_traffic(dom_name)
+    counters = measured_counters(dom_name)
+    traffic = None if counters is None else counters["bytes"]
     roofline = {"bound": "hbm", "kernel": dom_name,
                 "achieved": round(per[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(per[dom]["GBps"] / HBM_PEAK_GBS, 4),
@@ -284,6 +408,13 @@ def main():
                 "bytes_per_launch": BYTES_PER_CELL_PASS["f32"] * cells,
                 "avg_launch_us": {k: round(v["avg_us"], 3) for k, v in per.items()},
                 "step_GBps": round(2 * BYTES_PER_CELL_PASS["f32"] * cells * a.steps / t32 / 1e9, 1)}
+    if counters is not None and counters["valu_insts"]:
+        # the second limit: wave-level FP32 VALU issue (no packed FP32), one
+        # instruction per SIMD every 4 cycles: 256 CUs x 4 SIMDs x 2.4 GHz / 4
+        rate = counters["valu_insts"] / (per[dom]["avg_us"] * 1e-6) / 1e9
+        roofline["valu"] = {"insts_per_launch": counters["valu_insts"], "achieved": round(rate, 1),
+                            "peak": VALU_PEAK_GINST, "unit": "G wave-instructions/s",
+                            "frac": round(rate / VALU_PEAK_GINST, 4)}
     sim32.close()
 
     extra = {}
@@ -312,6 +443,12 @@ def main():
         extra["batch"] = batch_section(qw, W, torch, a.batch_steps, a.batch_single_steps)
     if not a.no_learned:
         extra["learned"] = learned_section(qw, W, torch)
+    if not a.no_unfused:
+        u = unfused_section(qw, wl, torch)
+        u["fused_ms_per_step"] = 1e3 * t32 / a.steps
+        u["speedup_fused_over_unfused"] = u["ms_per_step"] / u["fused_ms_per_step"]
+        u["speedup_fused_over_fft_only"] = u["fft_only_ms_per_step"] / u["fused_ms_per_step"]
+        extra["unfused_rocfft"] = u
 
     # oracle on a bounded sample: the same grid and field, a few steps
     import oracle

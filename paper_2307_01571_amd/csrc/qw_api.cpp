@@ -142,7 +142,10 @@ hipEvent_t pooled_event(qw_ctx h)
         h->event_pool.pop_back();
         return e;
     }
+    // timing-only events: no system-scope fence at record time, so the
+    // bracket does not add a cache writeback to the launch it measures
     hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess) return e;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
