@@ -466,7 +466,22 @@ def main():
     oracle.step_n(G, B, psi, n_cpu, wl.dt, wl.dt)
     cpu_s = time.perf_counter() - tc
     cpu_value = cells * n_cpu / cpu_s
-    log(f"oracle: {n_cpu} steps in {cpu_s:.1f} s on {oracle.get_threads()} threads -> {cpu_value:.3e} cell-steps/s")
+    n_threads = oracle.get_threads()
+    log(f"oracle: {n_cpu} steps in {cpu_s:.1f} s on {n_threads} threads -> {cpu_value:.3e} cell-steps/s")
+    # the same on one host thread: one step (the oracle's sums do not depend on the thread count)
+    oracle.set_threads(1)
+    tc = time.perf_counter()
+    oracle.step_n(G, B, psi, 1, wl.dt, wl.dt)
+    cpu1_s = time.perf_counter() - tc
+    oracle.set_threads(n_threads)
+    cpu1_value = cells / cpu1_s
+    log(f"oracle: 1 step in {cpu1_s:.1f} s on 1 thread -> {cpu1_value:.3e} cell-steps/s")
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
 
     out = {
         "metric": "spinor-cell steps/s at 2048^2 FP32 vs FP64 @1e-4 prob error; %HBM roofline",
@@ -486,9 +501,10 @@ def main():
                    "nx": wl.grid.nx, "ny": wl.grid.ny, "box_wavelengths": 64, "w0_wavelengths": 16,
                    "a0": wl.beam.a0, "dt": wl.dt, "steps": a.steps},
         "roofline": roofline,
-        "cpu_baseline": {"value": cpu_value, "unit": "cell-steps/s", "cores": oracle.get_threads(),
+        "cpu_baseline": {"value": cpu_value, "unit": "cell-steps/s", "cores": n_threads,
                          "kind": "oracle",
-                         "sample": f"{n_cpu} FP64 steps of the same 2048x2048 workload after 1 step"},
+                         "sample": f"{n_cpu} FP64 steps of the same 2048x2048 workload after 1 step",
+                         "one_thread_value": cpu1_value, "cpu_model": cpu_model},
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
