@@ -61,8 +61,8 @@ struct bshape {
     static constexpr int NT = N / E;
     static constexpr int L = 2 * NT;
     static constexpr int LINES = kBatchThreads / L;  // rows (RPW) or columns (TX) per tile
-    static constexpr int LLR = lds_len<N>::value + QW_LDS_EXTRA_ROW;
-    static constexpr int LLC = lds_len<N>::value + QW_LDS_EXTRA_COL;
+    static constexpr int LLR = lds_len<T, N>::value + QW_LDS_EXTRA_ROW;
+    static constexpr int LLC = lds_len<T, N>::value + QW_LDS_EXTRA_COL;
     static constexpr int lds_row = LINES * 2 * LLR;
     static constexpr int lds_col = LINES * 2 * LLC;
     static_assert(L <= kBatchThreads, "a line must fit one batched workgroup");

@@ -447,15 +447,26 @@ __device__ __forceinline__ void dft(cx<T>* x)
 template <int... R>
 struct sched {};
 
-// LDS padding: one extra element every 2^QW_LDS_PADSH breaks the
-// power-of-two strides of the exchanges
-#ifndef QW_LDS_PADSH
-#define QW_LDS_PADSH 5
+// LDS padding: one extra element every 2^sh elements breaks the
+// power-of-two strides of the exchanges.  Measured on MI355X: every 32
+// elements for 8-byte (float) elements, every 8 for 16-byte (double)
+// elements, whose stride-8 writes of the first exchange otherwise land on
+// the same banks (2048^2 FP64: rows 207 -> 190 us, columns 173 -> 164 us).
+#ifndef QW_LDS_PADSH_F32
+#define QW_LDS_PADSH_F32 5
 #endif
-__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> QW_LDS_PADSH); }
-template <int N>
+#ifndef QW_LDS_PADSH_F64
+#define QW_LDS_PADSH_F64 3
+#endif
+template <typename T>
+struct lds_pad {
+    static constexpr int sh = sizeof(T) == sizeof(float) ? QW_LDS_PADSH_F32 : QW_LDS_PADSH_F64;
+};
+template <typename T>
+__device__ __forceinline__ constexpr int lpad(int i) { return i + (i >> lds_pad<T>::sh); }
+template <typename T, int N>
 struct lds_len {
-    static constexpr int value = N + (N >> QW_LDS_PADSH);
+    static constexpr int value = N + (N >> lds_pad<T>::sh);
 };
 
 // Twiddles are stored per pass: for a pass (NS, R) with NS > 1 the entries
@@ -536,11 +547,11 @@ __device__ __forceinline__ void fft_exchange(cx<T> (&vc)[E], int t, cx<T>* lds)
         const int j = t + NT * b;
         const int base = (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lpad(base + r * NS)] = vc[b + r * B];
+        for (int r = 0; r < R; ++r) lds[lpad<T>(base + r * NS)] = vc[b + r * B];
     }
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) vc[m] = lds[lpad(t + NT * m)];
+    for (int m = 0; m < E; ++m) vc[m] = lds[lpad<T>(t + NT * m)];
     __syncthreads();
 }
 

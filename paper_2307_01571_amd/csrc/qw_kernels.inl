@@ -101,8 +101,8 @@ struct shape {
     static constexpr int TX = L >= 512 ? 1 : (L >= 128 ? QW_TX_COL : 256 / L);  // columns per workgroup
     // per-lane-group LDS buffer strides (elements); the extra elements move
     // the groups' buffers onto different banks
-    static constexpr int LLR = lds_len<N>::value + QW_LDS_EXTRA_ROW;
-    static constexpr int LLC = lds_len<N>::value + QW_LDS_EXTRA_COL;
+    static constexpr int LLR = lds_len<T, N>::value + QW_LDS_EXTRA_ROW;
+    static constexpr int LLC = lds_len<T, N>::value + QW_LDS_EXTRA_COL;
 };
 
 // ---------------------------------------------------------------------------
