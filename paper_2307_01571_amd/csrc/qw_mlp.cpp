@@ -3,6 +3,7 @@
 // back-propagation and the Adam step.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -40,6 +41,9 @@ struct Plan {
     std::vector<Layer> layer;
     // byte offsets
     size_t P, Mo, V, G, Wb, Wt, shift, scale, oshift, oscale, Xb, Xt, Z, H, Ht, Y, dYb, dYt, dZb, dZt, loss_part, loss;
+    size_t Kp;             // split-K parts of the weight gradients
+    int ks_max = 1;        // most K splits of a weight-gradient product
+    long long kp_net = 0;  // floats per net in Kp
     size_t total;
 };
 
@@ -115,6 +119,16 @@ Plan make_plan(const qw_mlp_shape& s)
     p.dZt = take(2 * nets * 2 * M * W);
     p.loss_part = take(4 * nets * (M / 64));
     p.loss = take(4 * nets);
+    // weight gradients sum over the batch (K = batch rows) on few output
+    // tiles: split K so that each net's product covers about 256 workgroups
+    // (independent of the number of nets, so a net's gradients do not
+    // depend on the ensemble it is trained in)
+    long long wmax = 0;
+    for (const Layer& y : p.layer) wmax = std::max(wmax, (long long)y.n_out * y.n_in);
+    const long long tiles = (W / 64) * (W / 64);
+    p.ks_max = (int)std::max(1LL, std::min(16LL, 256 / tiles));
+    p.kp_net = p.ks_max > 1 ? p.ks_max * wmax : 0;
+    p.Kp = take(4 * nets * p.kp_net);
     p.total = b;
     return p;
 }
@@ -288,10 +302,26 @@ hipError_t weight_grad(qw_mlp h, int l, const __bf16* dzt, long long s_dzt, cons
     g.N = y.n_in;
     g.K = Mp;
     g.Mpad = round64(y.n_out);
-    g.Cf = at<float>(h, p.G) + y.p_off;
-    g.sCf = p.np;
-    g.ldcf = y.n_in;
-    hipError_t e = qwm::launch_gemm(qwm::EPI_F32, g, p.s.n_nets, y.n_in, s);
+    float* dw = at<float>(h, p.G) + y.p_off;
+    // split K (the batch) into chunks of at least 256 rows, multiples of 64
+    int ks = std::min(p.ks_max, Mp / 256);
+    hipError_t e;
+    if (ks >= 2) {
+        const int chunk = round64((Mp + ks - 1) / ks);
+        ks = (Mp + chunk - 1) / chunk;
+        g.ksplit = ks;
+        g.k_chunk = chunk;
+        g.Cp = at<float>(h, p.Kp);
+        g.sCp_net = p.kp_net;
+        e = qwm::launch_gemm(qwm::EPI_PARTIAL, g, p.s.n_nets, y.n_in, s);
+        if (e == hipSuccess)
+            e = qwm::launch_ksum(g.Cp, p.kp_net, ks, y.n_out, y.n_in, dw, p.np, y.n_in, p.s.n_nets, s);
+    } else {
+        g.Cf = dw;
+        g.sCf = p.np;
+        g.ldcf = y.n_in;
+        e = qwm::launch_gemm(qwm::EPI_F32, g, p.s.n_nets, y.n_in, s);
+    }
     if (e == hipSuccess)
         e = qwm::launch_row_sums(dzt, s_dzt, Mp, y.n_out, B, at<float>(h, p.G) + y.b_off, p.np, p.s.n_nets, s);
     return e;

@@ -44,16 +44,19 @@ template <int EPI>
 __global__ __launch_bounds__(256) void gemm_nt(GemmArgs g)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int net = blockIdx.z;
+    const int split = EPI == EPI_PARTIAL ? (int)blockIdx.z % g.ksplit : 0;
+    const int net = EPI == EPI_PARTIAL ? (int)blockIdx.z / g.ksplit : (int)blockIdx.z;
     const int m0 = blockIdx.x * 64 + (w >> 1) * 32;
     const int n0 = blockIdx.y * 64 + (w & 1) * 32;
     const __bf16* A = g.A + net * g.sA;
     const __bf16* B = g.B + net * g.sB;
     const int ra = m0 + (lane & 31), rb = n0 + (lane & 31), kl = 8 * (lane >> 5);
+    const int kbeg = EPI == EPI_PARTIAL ? split * g.k_chunk : 0;
+    const int kend = EPI == EPI_PARTIAL ? min(g.K, kbeg + g.k_chunk) : g.K;
 
     f32x16 acc = {};
-    int k = 0;
-    for (; k + 64 <= g.K; k += 64) {
+    int k = kbeg;
+    for (; k + 64 <= kend; k += 64) {
         bf16x8 a[4], b[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(256) void gemm_nt(GemmArgs g)
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[u], acc, 0, 0, 0);
     }
-    for (; k < g.K; k += 16) {
+    for (; k < kend; k += 16) {
         const bf16x8 a = load_row8(A, ra, g.M, g.lda, k + kl);
         const bf16x8 b = load_row8(B, rb, g.N, g.ldb, k + kl);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
@@ -88,6 +91,8 @@ __global__ __launch_bounds__(256) void gemm_nt(GemmArgs g)
             float o = 0.0f;
             if constexpr (EPI == EPI_F32) {
                 if (in) Cf[(size_t)m * g.ldcf + n] = c;
+            } else if constexpr (EPI == EPI_PARTIAL) {
+                if (in) g.Cp[net * g.sCp_net + ((size_t)split * g.M + m) * g.N + n] = c;
             } else if constexpr (EPI == EPI_HIDDEN) {
                 const float z = c + bias;
                 if (in && Cf) Cf[(size_t)m * g.ldcf + n] = z;
@@ -242,8 +247,36 @@ hipError_t launch_gemm(int epi, const GemmArgs& g, int nets, int ncover, hipStre
     case EPI_HIDDEN: hipLaunchKernelGGL(gemm_nt<EPI_HIDDEN>, grid, block, 0, s, g); break;
     case EPI_OUT: hipLaunchKernelGGL(gemm_nt<EPI_OUT>, grid, block, 0, s, g); break;
     case EPI_GELU_BWD: hipLaunchKernelGGL(gemm_nt<EPI_GELU_BWD>, grid, block, 0, s, g); break;
+    case EPI_PARTIAL: {
+        if (g.ksplit < 1 || g.k_chunk < 16 || g.k_chunk % 16 != 0) return hipErrorInvalidValue;
+        const dim3 gridp(grid.x, grid.y, nets * g.ksplit);
+        hipLaunchKernelGGL(gemm_nt<EPI_PARTIAL>, gridp, block, 0, s, g);
+        break;
+    }
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// fixed-order sum of the split-K parts
+__global__ __launch_bounds__(256) void ksum(const float* part, long long s_part_net, int ksplit, int M, int N,
+                                            float* C, long long s_c, int ldc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int net = blockIdx.y;
+    if (i >= M * N) return;
+    const float* p = part + net * s_part_net + i;
+    float acc = 0.0f;
+    for (int sp = 0; sp < ksplit; ++sp) acc += p[(size_t)sp * M * N];
+    const int m = i / N, n = i - m * N;
+    C[net * s_c + (size_t)m * ldc + n] = acc;
+}
+
+hipError_t launch_ksum(const float* part, long long s_part_net, int ksplit, int M, int N, float* C, long long s_c,
+                       int ldc, int nets, hipStream_t s)
+{
+    hipLaunchKernelGGL(ksum, dim3((M * N + 255) / 256, nets), dim3(256), 0, s, part, s_part_net, ksplit, M, N, C, s_c,
+                       ldc);
     return hipGetLastError();
 }
 

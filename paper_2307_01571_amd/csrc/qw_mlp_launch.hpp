@@ -9,7 +9,7 @@ namespace qwm {
 constexpr int kInPad = 16;   // input features and outputs are padded to one K step of the product
 constexpr int kMaxLayers = 17;
 
-enum { EPI_F32 = 0, EPI_HIDDEN = 1, EPI_OUT = 2, EPI_GELU_BWD = 3 };
+enum { EPI_F32 = 0, EPI_HIDDEN = 1, EPI_OUT = 2, EPI_GELU_BWD = 3, EPI_PARTIAL = 4 };
 
 // C[m][n] = sum_k A[m][k] B[n][k]; operands bfloat16, K-contiguous, K a
 // multiple of 16, leading dimensions multiples of 8; per-net strides in
@@ -19,6 +19,9 @@ enum { EPI_F32 = 0, EPI_HIDDEN = 1, EPI_OUT = 2, EPI_GELU_BWD = 3 };
 //   EPI_OUT       y = C + bias -> Cf; with T: d = y - T, g = gscale d -> Cb, Ct,
 //                 per-workgroup sums of d^2 -> loss_part
 //   EPI_GELU_BWD  g = C gelu'(Z) -> Cb, Ct
+//   EPI_PARTIAL   split-K part: blockIdx.z = net ksplit + split sums k in
+//                 [split k_chunk, (split + 1) k_chunk) into the dense M x N
+//                 slice Cp + net sCp_net + split M N (summed by launch_ksum)
 // Cb rows [M, Mpad) and columns [N, ldcb) are written as zeros, likewise
 // Ct rows [N, nct) and columns [M, Mpad): the padding the next product reads.
 struct GemmArgs {
@@ -48,6 +51,9 @@ struct GemmArgs {
     float* loss_part;
     long long sLoss;
     float gscale;
+    int ksplit, k_chunk;  // EPI_PARTIAL only
+    float* Cp;
+    long long sCp_net;
 };
 
 // where one layer's weights sit in the flat FP32 parameters and in the
@@ -74,6 +80,9 @@ struct AdamArgs {
 };
 
 hipError_t launch_gemm(int epi, const GemmArgs& g, int nets, int ncover, hipStream_t s);
+// C[net][m][ldc] = sum over split (in order) of part[net][split][m][N]
+hipError_t launch_ksum(const float* part, long long s_part_net, int ksplit, int M, int N, float* C, long long s_c,
+                       int ldc, int nets, hipStream_t s);
 hipError_t launch_prep_input(const float* x, int B, int n_in, int Mpad, const float* shift, const float* scale,
                              __bf16* xb, __bf16* xt, hipStream_t s);
 hipError_t launch_row_sums(const __bf16* in, long long s_in, int ld, int rows, int M, float* out, long long s_out,

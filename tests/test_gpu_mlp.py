@@ -17,7 +17,10 @@ Bars (bfloat16 unit roundoff u = 2^-8 relative spacing, FP32 accumulation):
 * Adam: the updated FP32 parameters equal the oracle's Adam step on the
   kernel's own gradients to FP32 rounding (4e-6 relative);
 * nets of an ensemble are independent: each net's gradients equal those of a
-  one-net ensemble holding its parameters, bit for bit.
+  one-net ensemble holding its parameters, bit for bit;
+* weight gradients over a large batch (split into chunks summed in a fixed
+  order): the same 1e-3 bar, the FP32 sums now over K = 2000 terms
+  (K 2^-24 ~ 1.2e-4 at worst).
 """
 import numpy as np
 import pytest
@@ -116,6 +119,28 @@ def test_gradients_match_oracle():
             print(f"  net {k} layer {li}: dW rel {ew:.2e}, db rel {eb:.2e}, vs plain FP64 {e64:.2e}")
             assert ew <= 1e-3 and eb <= 1e-3
             assert e64 <= 2e-2
+    net.close()
+
+
+def test_gradients_match_oracle_split_k():
+    # a batch of 2000 rows at width 256: the weight-gradient products split
+    # the batch into chunks that a second kernel sums in a fixed order
+    import torch
+    print_case(test="mlp_gradients_split_k", batch=2000, width=256, depth=4)
+    net, params, x, t, shift, scale = make_net(n_nets=2, width=256, depth=4, B=2000, seed=3)
+    g, loss = net.gradients(torch.from_numpy(x), torch.from_numpy(t))
+    g = g.double().cpu().numpy()
+    loss = loss.double().cpu().numpy()
+    for k in range(params.shape[0]):
+        layers = M.unflatten(params[k], 5, 256, 4, 6)
+        lref, _, gref = M.loss_and_grads(layers, x, t, shift, scale, emulate_bf16=True)
+        assert abs(loss[k] - lref) <= 1e-3 * lref
+        got = M.unflatten(g[k], 5, 256, 4, 6)
+        for li, ((gw, gb), (rw, rb)) in enumerate(zip(got, gref)):
+            ew = np.linalg.norm(gw - rw) / np.linalg.norm(rw)
+            eb = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
+            print(f"  net {k} layer {li}: dW rel {ew:.2e}, db rel {eb:.2e}")
+            assert ew <= 1e-3 and eb <= 1e-3
     net.close()
 
 
