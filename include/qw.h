@@ -155,7 +155,13 @@ int qw_init_packet(qw_ctx h, void *psi, const qw_packet *e, void *hip_stream);
  * dt may be negative (backward propagation); dt = 0 and n = 0 leave psi as is
  * (n = 0 enqueues nothing).  2n + 1 kernels: one row pass V(t0, dt/2) F_x,
  * then n column passes F_y^-1 K(dt) F_y interleaved with n - 1 row passes
- * F_x V(t_k, dt) F_x^-1, and a last row pass V(t_n, dt/2) F_x^-1. */
+ * F_x V(t_k, dt) F_x^-1, and a last row pass V(t_n, dt/2) F_x^-1.
+ * With n > 64 and timing off, the middle steps run as replays of one
+ * HIP graph of 64 (column, row) pass pairs, whose row passes read t_k from
+ * a step clock in the workspace; the graph is captured on a stream of the
+ * library's own at the first such call and again whenever psi, the beam or
+ * the frame differ from that capture's (the graph and the stream live until
+ * qw_destroy).  The results equal those of direct launches bit for bit. */
 int qw_step_n(qw_ctx h, void *psi, int64_t n, double t0, double dt, void *hip_stream);
 
 /* Observables of psi (not modified) into out_host (host memory), laid out as

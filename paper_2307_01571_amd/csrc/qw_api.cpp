@@ -87,6 +87,12 @@ struct qw_ctx_s {
     bool timing = false;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
+    // the step loop's captured chunk: valid for exec_psi and the beam/frame
+    // state of args_version
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* exec_psi = nullptr;
+    unsigned long long args_version = 0, exec_version = 0;
 };
 
 namespace {
@@ -227,6 +233,67 @@ qw::ColArgs col_args(qw_ctx h, void* psi)
     return a;
 }
 
+// middle steps per captured chunk of the step loop
+constexpr int kGraphSteps = 64;
+
+// the step loop's device clock: 4 doubles at the end of the scalars slot
+qw::StepClock* step_clock(qw_ctx h)
+{
+    return reinterpret_cast<qw::StepClock*>(reinterpret_cast<double*>(h->ws + h->lay.scalars) + 248);
+}
+
+void drop_graph(qw_ctx h)
+{
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    h->exec = nullptr;
+    h->exec_psi = nullptr;
+}
+
+// One chunk of kGraphSteps middle steps (column pass, then the row pass
+// V(t_k, dt) with k read from the device clock) and the clock's advance,
+// captured on the library's own stream; recaptured when psi, the beam or
+// the frame change.  r and c are the step loop's argument blocks.
+hipError_t ensure_graph(qw_ctx h, void* psi, qw::RowArgs r, const qw::ColArgs& c)
+{
+    if (h->exec && h->exec_psi == psi && h->exec_version == h->args_version) return hipSuccess;
+    drop_graph(h);
+    hipError_t e = hipSuccess;
+    if (!h->cap) {
+        int prev = 0;
+        e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != h->device) e = hipSetDevice(h->device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+        if (prev != h->device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+    }
+    qw::StepClock* clk = step_clock(h);
+    r.clock = clk;
+    r.t0 = 0.0;
+    r.dt = 0.0;
+    r.tau_frac = 1.0;  // V(t_k, dt/2) V(t_k, dt/2) = V(t_k, dt)
+    e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j) {
+        le = launch_col(h, qw::COL_PROP, c, h->cap);
+        r.k = j;
+        if (le == hipSuccess) le = launch_row(h, qw::ROW_MID, r, h->cap);
+    }
+    if (le == hipSuccess) le = qw::launch_clock_advance(clk, kGraphSteps, h->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap, &g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->exec = nullptr;
+        return e;
+    }
+    h->exec_psi = psi;
+    h->exec_version = h->args_version;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -298,6 +365,7 @@ int qw_set_beam(qw_ctx h, const qw_beam* b)
     h->b = *b;
     h->beam_set = true;
     h->tables_dirty = true;
+    ++h->args_version;
     return QW_OK;
 }
 
@@ -309,6 +377,7 @@ int qw_set_frame(qw_ctx h, const qw_frame* f)
     const int rc = qwh::check_frame(*f, h->g.c, &msg);
     if (rc != QW_OK) return fail(h, rc, "%s", msg.c_str());
     h->frame = *f;
+    ++h->args_version;
     return QW_OK;
 }
 
@@ -360,7 +429,17 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     r.k = 0;
     r.tau_frac = 0.5;
     e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_FIRST, r, s); });
-    for (int64_t k = 1; k <= n && e == hipSuccess; ++k) {
+    int64_t k0 = 1;
+    if (e == hipSuccess && !h->timing && n - 1 >= kGraphSteps) {
+        // middle steps 1 .. chunks kGraphSteps as replays of one captured chunk
+        qw::StepClock* clk = step_clock(h);
+        e = qw::launch_clock_set(clk, t0, dt, 1, s);
+        if (e == hipSuccess) e = ensure_graph(h, psi, r, c);
+        const int64_t chunks = (n - 1) / kGraphSteps;
+        for (int64_t q = 0; q < chunks && e == hipSuccess; ++q) e = hipGraphLaunch(h->exec, s);
+        k0 += chunks * kGraphSteps;
+    }
+    for (int64_t k = k0; k <= n && e == hipSuccess; ++k) {
         e = timed(h, 1, s, [&] { return launch_col(h, qw::COL_PROP, c, s); });
         if (e != hipSuccess) break;
         r.k = k;
@@ -466,6 +545,8 @@ const char* qw_last_error(qw_ctx h)
 void qw_destroy(qw_ctx h)
 {
     if (!h) return;
+    drop_graph(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     for (auto& t : h->timed) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);

@@ -182,7 +182,7 @@ int make_batch_layout(const qw_instance* inst, int n, BatchLayout* L, std::strin
         w = align_up(w + bytes);
         return at;
     };
-    L->time = take(sizeof(qw::BatchTime));
+    L->time = take(sizeof(qw::StepClock));
     L->desc = take(sizeof(qw::BatchInst) * (size_t)n);
     L->row_items = take(sizeof(uint32_t) * L->row_items_h.size());
     L->col_items = take(sizeof(uint32_t) * L->col_items_h.size());
@@ -271,7 +271,7 @@ int bhip(qw_batch b, hipError_t e, const char* what)
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-qw::BatchTime* dev_time(qw_batch b) { return reinterpret_cast<qw::BatchTime*>(b->ws + b->lay.time); }
+qw::StepClock* dev_time(qw_batch b) { return reinterpret_cast<qw::StepClock*>(b->ws + b->lay.time); }
 qw::BatchInst* dev_desc(qw_batch b) { return reinterpret_cast<qw::BatchInst*>(b->ws + b->lay.desc); }
 
 void drop_graph(qw_batch b)
@@ -418,7 +418,7 @@ hipError_t ensure_graph(qw_batch b, char* psi)
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
     for (int j = 0; j < b->graph_steps && le == hipSuccess; ++j) le = middle_step(b, psi, j, true, b->cap);
-    if (le == hipSuccess) le = qw::launch_batch_advance(dev_time(b), b->graph_steps, b->cap);
+    if (le == hipSuccess) le = qw::launch_clock_advance(dev_time(b), b->graph_steps, b->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);
     if (le != hipSuccess) e = le;
@@ -529,7 +529,7 @@ int qw_batch_init(qw_batch* out, const qw_instance* inst, int32_t n, void* works
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ws + Y.col_items, Y.col_items_h.data(), sizeof(uint32_t) * Y.col_items_h.size(),
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = qw::launch_batch_set_time(dev_time(b), 0.0, 0.0, 0, s);
+    if (e == hipSuccess) e = qw::launch_clock_set(dev_time(b), 0.0, 0.0, 0, s);
     if (e == hipSuccess) e = upload_desc(b, s);  // waits for the stream
     if (e != hipSuccess) {
         bfail(nullptr, QW_E_DEVICE, "batch set-up: %s", hipGetErrorString(e));
@@ -583,7 +583,7 @@ int qw_batch_step_n(qw_batch b, void* psi, int64_t n, double t0, double dt, void
     rc = ensure_ktab(b, dt, s);
     if (rc != QW_OK) return rc;
     // the graph replays start at step 1
-    e = qw::launch_batch_set_time(dev_time(b), t0, dt, 1, s);
+    e = qw::launch_clock_set(dev_time(b), t0, dt, 1, s);
     // V(t0, dt/2) then F_x
     qw::BatchLaunch r = launch_rows(b, base, base);
     r.j = 0;
@@ -711,7 +711,7 @@ int qw_batch_autotune(qw_batch b, const void* psi, double dt, int32_t reps, doub
     if (e == hipSuccess) e = hipEventCreate(&ev1);
     if (e == hipSuccess) e = hipMemcpyAsync(plane, psi, b->lay.state_bytes, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) rc = ensure_ktab(b, dt, s);
-    if (e == hipSuccess && rc == QW_OK) e = qw::launch_batch_set_time(dev_time(b), 0.0, dt, 0, s);
+    if (e == hipSuccess && rc == QW_OK) e = qw::launch_clock_set(dev_time(b), 0.0, dt, 0, s);
     int rows = 0;
     auto put = [&](double kind, double a, double v, double us) {
         if (report && (rows + 1) * 4 <= report_len) {

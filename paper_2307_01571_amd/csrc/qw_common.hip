@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kRedThreads) void batch_obs_finish(const BatchInst*
     obs_finish_body(I.row.rownorm, I.row.ny, I.col.partial, I.ntile_col, stride, n_max, I.scalars + 8, acc, red);
 }
 
-__global__ void batch_set_time(BatchTime* t, double t0, double dt, long long k)
+__global__ void clock_set(StepClock* t, double t0, double dt, long long k)
 {
     if (threadIdx.x == 0) {
         t->t0 = t0;
@@ -102,7 +102,7 @@ __global__ void batch_set_time(BatchTime* t, double t0, double dt, long long k)
     }
 }
 
-__global__ void batch_advance(BatchTime* t, long long steps)
+__global__ void clock_advance(StepClock* t, long long steps)
 {
     if (threadIdx.x == 0) t->k_base += steps;
 }
@@ -133,15 +133,15 @@ hipError_t launch_batch_obs_finish(const BatchInst* inst, int n, int stride, int
     return hipGetLastError();
 }
 
-hipError_t launch_batch_set_time(BatchTime* t, double t0, double dt, long long k, hipStream_t s)
+hipError_t launch_clock_set(StepClock* t, double t0, double dt, long long k, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_set_time, dim3(1), dim3(64), 0, s, t, t0, dt, k);
+    hipLaunchKernelGGL(clock_set, dim3(1), dim3(64), 0, s, t, t0, dt, k);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_advance(BatchTime* t, long long steps, hipStream_t s)
+hipError_t launch_clock_advance(StepClock* t, long long steps, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_advance, dim3(1), dim3(64), 0, s, t, steps);
+    hipLaunchKernelGGL(clock_advance, dim3(1), dim3(64), 0, s, t, steps);
     return hipGetLastError();
 }
 

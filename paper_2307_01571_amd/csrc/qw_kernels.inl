@@ -305,6 +305,11 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
 {
     using S = shape<T, N>;
     __shared__ cx<T> lds[S::RPW * 2 * S::LLR];
+    if (a.clock) {  // a replayed chunk of steps: its time is kept on the device
+        a.t0 = a.clock->t0;
+        a.dt = a.clock->dt;
+        a.k += a.clock->k_base;
+    }
     row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM>(a, blockIdx.x, lds, threadIdx.x);
 }
 

@@ -25,6 +25,17 @@ struct FullBeam {
     int longitudinal;
 };
 
+// Device-resident time of a propagation.  A graph-captured chunk of steps
+// takes t0, dt and the base k_base of the step index from here and advances
+// k_base by its length at its end, so one captured chunk replays for every
+// chunk of a run.  (Batched form: V is taken at t0 + k dt with
+// k = (use_counter ? k_base : 0) + j.)
+struct StepClock {
+    double t0, dt;
+    long long k_base;
+    long long pad_;
+};
+
 struct RowArgs {
     const void* src;          // [ny][nx][4] complex T
     void* dst;                // may equal src (in place)
@@ -40,6 +51,7 @@ struct RowArgs {
     int beam_mode;
     int ny;
     FullBeam full;            // beam_mode == QW_BEAM_GAUSSIAN_FULL_
+    const StepClock* clock;   // if set (graph replays): t0 and dt from here, k offset by clock->k_base
 };
 
 struct ColArgs {
@@ -96,16 +108,6 @@ struct BatchInst {
     int pad_;
 };
 
-// Device-resident time of a batched propagation: V is taken at t0 + k dt
-// with k = (use_counter ? k_base : 0) + j.  A graph-captured chunk of steps
-// reads k_base and advances it by its length at its end, so one captured
-// chunk replays for every chunk of a run.
-struct BatchTime {
-    double t0, dt;
-    long long k_base;
-    long long pad_;
-};
-
 struct BatchLaunch {
     const BatchInst* __restrict__ inst;
     const uint32_t* __restrict__ items;  // (instance << 16) | tile
@@ -115,7 +117,7 @@ struct BatchLaunch {
     int pad_;
     char* src;        // state bases; dst may equal src
     char* dst;
-    const BatchTime* time;
+    const StepClock* time;
     double tau_frac;
 };
 
@@ -153,7 +155,7 @@ hipError_t launch_batch_sum_rows(const BatchInst* inst, int n, hipStream_t s);
 // batched: per instance, scalars[8 ..] = observables from its rows and column partials
 hipError_t launch_batch_obs_finish(const BatchInst* inst, int n, int stride, int n_max, hipStream_t s);
 // batched time: set (t0, dt, k_base), or advance k_base
-hipError_t launch_batch_set_time(BatchTime* t, double t0, double dt, long long k, hipStream_t s);
-hipError_t launch_batch_advance(BatchTime* t, long long steps, hipStream_t s);
+hipError_t launch_clock_set(StepClock* t, double t0, double dt, long long k, hipStream_t s);
+hipError_t launch_clock_advance(StepClock* t, long long steps, hipStream_t s);
 
 }  // namespace qw

@@ -179,6 +179,40 @@ def test_split_calls_agree():
     assert rel_l2(b.state(), a.state()) <= 1e-13
 
 
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_graph_replays_equal_direct_launches(prec):
+    # 150 steps: two replays of the captured 64-step chunk plus 21 direct
+    # steps; with per-launch timing on the loop launches every step
+    # directly.  Same kernels, same step times: bitwise equal states.  Then
+    # a new beam (recapture) and a second state array (another capture).
+    wl = W.small_parity()
+    print_case(test="graph_replays", prec=prec)
+    a = qw.Sim(wl.grid, prec, beam=wl.beam)
+    b = qw.Sim(wl.grid, prec, beam=wl.beam)
+    a.init_packet(wl.packet)
+    b.init_packet(wl.packet)
+    qw.qw_kernel_timing(b.ctx, True)
+    a.step(150, 0.0, wl.dt)
+    b.step(150, 0.0, wl.dt)
+    qw.qw_kernel_times(b.ctx, b.stream())
+    assert np.array_equal(a.state(), b.state())
+    beam2 = strong_beam(w0=1.5, a0=0.8)
+    a.set_beam(beam2)
+    b.set_beam(beam2)
+    a.step(130, 150 * wl.dt, wl.dt)
+    b.step(130, 150 * wl.dt, wl.dt)
+    qw.qw_kernel_times(b.ctx, b.stream())
+    assert np.array_equal(a.state(), b.state())
+    other = a.psi.clone()
+    a.psi, other = other, a.psi
+    a.step(70, 280 * wl.dt, wl.dt)
+    b.step(70, 280 * wl.dt, wl.dt)
+    qw.qw_kernel_times(b.ctx, b.stream())
+    assert np.array_equal(a.state(), b.state())
+    a.close()
+    b.close()
+
+
 def test_n_zero_and_dt_zero():
     wl = W.small_parity()
     print_case(test="n0_dt0")
