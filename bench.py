@@ -349,8 +349,8 @@ def main():
                          "128 MiB written), the reference for bandwidth and traffic counters")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the workload does not "
-              "shard across GPUs in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the 2048^2 propagation is "
+              "measured on a single GPU, with no sharding across GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
