@@ -96,7 +96,7 @@ def test_mid_grid_full_run_f32_probabilities(name):
 
 
 def test_large_grid_full_run_f32_vs_f64():
-    """The spec workload: 2048^2, 5e4 steps; FP32 against the GPU FP64 run."""
+    """The throughput workload (2048^2, 5e4 steps, the launch sequence bench.py times): FP32 against the GPU FP64 run."""
     wl = W.large()
     _, o64 = run_gpu(wl, qw.QW_F64, wl.steps, 0.0)
     _, o32 = run_gpu(wl, qw.QW_F32, wl.steps, 0.0)
