@@ -29,7 +29,12 @@
  *     waiting, except qw_observables, which waits for its own results;
  *   - every function returns QW_OK (0) or a negative QW_E_* code, never
  *     throws and never exits; argument errors are reported before anything
- *     is enqueued; qw_last_error(ctx) describes the last failure.
+ *     is enqueued; qw_last_error(ctx) describes the last failure;
+ *   - a context (likewise a batch) is not thread-safe: calls on one context
+ *     from several host threads must be serialised by the caller; distinct
+ *     contexts are independent.  Work enqueued on different streams for the
+ *     same context or workspace (its tables, step clock and scratch plane)
+ *     must not overlap on the device.
  */
 #ifndef QW_H
 #define QW_H
