@@ -161,7 +161,8 @@ int qw_init_packet(qw_ctx h, void *psi, const qw_packet *e, void *hip_stream);
  * (n = 0 enqueues nothing).  2n + 1 kernels: one row pass V(t0, dt/2) F_x,
  * then n column passes F_y^-1 K(dt) F_y interleaved with n - 1 row passes
  * F_x V(t_k, dt) F_x^-1, and a last row pass V(t_n, dt/2) F_x^-1.
- * With n > 64 and timing off, the middle steps run as replays of one
+ * With n > 64, timing off and hip_stream not being captured by the caller,
+ * the middle steps run as replays of one
  * HIP graph of 64 (column, row) pass pairs, whose row passes read t_k from
  * a step clock in the workspace; the graph is captured on a stream of the
  * library's own at the first such call and again whenever psi, the beam or

@@ -430,7 +430,15 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     r.tau_frac = 0.5;
     e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_FIRST, r, s); });
     int64_t k0 = 1;
-    if (e == hipSuccess && !h->timing && n - 1 >= kGraphSteps) {
+    // a caller capturing its own stream (or a stream whose state cannot be
+    // queried) gets the plain launches
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    bool replay = !h->timing && n - 1 >= kGraphSteps;
+    if (replay && hipStreamIsCapturing(s, &cap_status) != hipSuccess) {
+        (void)hipGetLastError();
+        replay = false;
+    }
+    if (e == hipSuccess && replay && cap_status == hipStreamCaptureStatusNone) {
         // middle steps 1 .. chunks kGraphSteps as replays of one captured chunk
         qw::StepClock* clk = step_clock(h);
         e = qw::launch_clock_set(clk, t0, dt, 1, s);

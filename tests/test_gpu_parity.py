@@ -213,6 +213,32 @@ def test_graph_replays_equal_direct_launches(prec):
     b.close()
 
 
+def test_step_loop_captured_by_the_caller():
+    # qw_step_n inside the caller's own graph capture (torch.cuda.graph):
+    # plain launches are recorded; every replay, with eager work and
+    # synchronisation in between, equals the same call made eagerly
+    import torch
+    wl = W.small_parity()
+    print_case(test="caller_capture")
+    a = qw.Sim(wl.grid, F32, beam=wl.beam)
+    b = qw.Sim(wl.grid, F32, beam=wl.beam)
+    for sim in (a, b):
+        sim.init_packet(wl.packet)
+        sim.step(1, 0.0, wl.dt)  # tables built outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        a.step(100, wl.dt, wl.dt)
+    for r in range(3):
+        g.replay()
+        b.step(100, wl.dt, wl.dt)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.state(), b.state()), f"replay {r}"
+    del g
+    a.close()
+    b.close()
+
+
 def test_n_zero_and_dt_zero():
     wl = W.small_parity()
     print_case(test="n0_dt0")
