@@ -249,7 +249,8 @@ int qw_batch_init_packets(qw_batch b, void *psi, const qw_packet *packets, void 
  * same sequence as qw_step_n; asynchronous.  The middle steps run as
  * replays of a captured graph of graph_steps (column pass, row pass) pairs
  * whose step index comes from a device counter; the rest are direct
- * launches. */
+ * launches, and so is everything while timing is on or while the caller
+ * captures hip_stream itself. */
 int qw_batch_step_n(qw_batch b, void *psi, int64_t n, double t0, double dt, void *hip_stream);
 
 /* Observables of every instance (specs: n entries, one n_max for all) into

@@ -590,7 +590,15 @@ int qw_batch_step_n(qw_batch b, void* psi, int64_t n, double t0, double dt, void
     r.tau_frac = 0.5;
     if (e == hipSuccess) e = timed(b, 0, s, [&] { return row_pass(b, qw::ROW_FIRST, r, s); });
     int64_t k = 1;
-    if (e == hipSuccess && !b->timing && b->graph_steps > 0 && n - 1 >= b->graph_steps) {
+    // a caller capturing its own stream (or a stream whose state cannot be
+    // queried) gets the plain launches
+    bool replay = !b->timing && b->graph_steps > 0 && n - 1 >= b->graph_steps;
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    if (replay && hipStreamIsCapturing(s, &cap_status) != hipSuccess) {
+        (void)hipGetLastError();
+        replay = false;
+    }
+    if (e == hipSuccess && replay && cap_status == hipStreamCaptureStatusNone) {
         e = ensure_graph(b, base);
         const int64_t chunks = (n - 1) / b->graph_steps;
         for (int64_t c = 0; c < chunks && e == hipSuccess; ++c) e = hipGraphLaunch(b->exec, s);
