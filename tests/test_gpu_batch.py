@@ -134,6 +134,33 @@ def test_batch_f32_is_bitwise_the_single_instance_path(launch):
     bt.close()
 
 
+def test_batch_step_loop_captured_by_the_caller():
+    # qw_batch_step_n inside the caller's own graph capture (torch.cuda.graph):
+    # plain launches are recorded even where the batch would replay its own
+    # graph (20 steps, chunks of 8); every replay equals the eager call
+    import torch
+    cases = mixed_instances(MIXED[:3], seed=17)
+    print_case(test="batch_caller_capture")
+    a = make_batch(cases, F32)
+    b = make_batch(cases, F32)
+    for bt in (a, b):
+        bt.set_launch(0, 0, 8)
+        bt.step(1, 0.0, W.DT)  # descriptors and kinetic tables set up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        a.step(20, W.DT, W.DT)
+    for r in range(3):
+        g.replay()
+        b.step(20, W.DT, W.DT)
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert np.array_equal(a.state(i), b.state(i)), (r, i)
+    del g
+    a.close()
+    b.close()
+
+
 def test_batch_runs_continue_across_calls():
     """Two calls of n1 and n2 steps from t0 and t0 + n1 dt equal the oracle's
     n1 + n2 steps up to the merged half steps' rounding."""
