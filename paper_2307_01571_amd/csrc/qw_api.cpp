@@ -1,7 +1,8 @@
 // qw_api.cpp -- host engine behind the C ABI of include/qw.h: argument
 // validation, workspace carving, table set-up and the launch sequence of the
-// split-operator step.  No device memory is allocated here; every launch goes
-// to the caller's stream.
+// split-operator step (direct launches, or replays of one captured chunk of
+// the step loop).  No device memory is allocated here; every launch and
+// replay goes to the caller's stream.
 #include "qw.h"
 
 #include <hip/hip_runtime.h>
