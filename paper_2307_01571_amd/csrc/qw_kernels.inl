@@ -521,12 +521,46 @@ __device__ void fill_pass_twiddles(cx<double>* tmp, int i, int off)
     if constexpr (sizeof...(Rest) > 0) fill_pass_twiddles<NS * R, Rest...>(tmp, i, off + (NS > 1 ? NS * R : 0));
 }
 
+// (c, s) rounded to float jointly: among the floats within two units in the
+// last place of each, the pair whose c^2 + s^2 is closest to 1 (ties: the
+// one closest to (c, s)).  Rounded separately, a twiddle's squared magnitude
+// is off by up to 1.2e-7, a bias the norm of an FP32 transform would carry.
+__device__ inline cx<float> unit_pair_f32(double c, double s)
+{
+    float cs[5], ss[5];
+    cs[2] = (float)c;
+    ss[2] = (float)s;
+    cs[1] = nextafterf(cs[2], -INFINITY);
+    cs[0] = nextafterf(cs[1], -INFINITY);
+    cs[3] = nextafterf(cs[2], INFINITY);
+    cs[4] = nextafterf(cs[3], INFINITY);
+    ss[1] = nextafterf(ss[2], -INFINITY);
+    ss[0] = nextafterf(ss[1], -INFINITY);
+    ss[3] = nextafterf(ss[2], INFINITY);
+    ss[4] = nextafterf(ss[3], INFINITY);
+    cx<float> best{cs[2], ss[2]};
+    double be = fabs((double)cs[2] * cs[2] + (double)ss[2] * ss[2] - 1.0);
+    double bd = fabs(cs[2] - c) + fabs(ss[2] - s);
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b) {
+            const double e = fabs((double)cs[a] * cs[a] + (double)ss[b] * ss[b] - 1.0);
+            const double d = fabs(cs[a] - c) + fabs(ss[b] - s);
+            if (e < be || (e == be && d < bd)) {
+                best = cx<float>{cs[a], ss[b]};
+                be = e;
+                bd = d;
+            }
+        }
+    return best;
+}
+
 template <typename T, int... R>
 __device__ void pass_twiddle(sched<R...>, cx<T>* tw, int i)
 {
     cx<double> v{1.0, 0.0};
     fill_pass_twiddles<1, R...>(&v, i, 0);
-    tw[i] = cx<T>{(T)v.re, (T)v.im};
+    if constexpr (sizeof(T) == sizeof(float)) tw[i] = unit_pair_f32(v.re, v.im);
+    else tw[i] = cx<T>{(T)v.re, (T)v.im};
 }
 
 template <typename T, int N, typename SCH = typename plan<T, N>::S>
