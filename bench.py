@@ -75,6 +75,27 @@ def measured_counters(kernel: str):
     return {"bytes": k["read_bytes"] + k["write_bytes"], "valu_insts": k.get("valu_insts")}
 
 
+def copy_rate(torch, wl, n=50):
+    """torch's plain device copy of one 2048^2 FP32 state (128 MiB read and
+    128 MiB written): average microseconds, GB/s and bytes moved per copy."""
+    src = torch.empty((wl.grid.ny, wl.grid.nx, 4), dtype=torch.complex64, device="cuda")
+    src.real.fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(n):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / n
+    nbytes = 2 * src.numel() * src.element_size()
+    del src, dst
+    return us, nbytes / (us * 1e-6) / 1e9, nbytes
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -366,23 +387,9 @@ def main():
     cells = wl.grid.nx * wl.grid.ny
 
     if a.copy_probe:
-        src = torch.empty((wl.grid.ny, wl.grid.nx, 4), dtype=torch.complex64, device="cuda")
-        src.real.fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        n = 50
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(n):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        us = ev0.elapsed_time(ev1) * 1e3 / n
-        nbytes = 2 * src.numel() * src.element_size()
+        us, gbs, nbytes = copy_rate(torch, wl)
         print(json.dumps({"probe": "torch copy", "bytes_read": nbytes // 2, "bytes_written": nbytes // 2,
-                          "avg_us": us, "GBps": nbytes / (us * 1e-6) / 1e9}), flush=True)
+                          "avg_us": us, "GBps": gbs}), flush=True)
         return
 
     log(f"FP32 {wl.grid.nx}x{wl.grid.ny}: warmup {a.warmup}, timed {a.steps} steps")
@@ -417,6 +424,12 @@ def main():
                             "peak": VALU_PEAK_GINST, "unit": "G wave-instructions/s",
                             "frac": round(rate / VALU_PEAK_GINST, 4)}
     sim32.close()
+    # the same traffic as one pass, moved by a plain copy: the attainable HBM rate
+    copy_us, copy_gbs, _ = copy_rate(torch, wl)
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(per[dom]["GBps"] / copy_gbs, 4)
+    log(f"plain copy of the state: {copy_us:.2f} us, {copy_gbs:.0f} GB/s; {dom} pass at "
+        f"{roofline['frac_of_copy']:.3f} of it")
 
     extra = {}
     if not a.no_f64:
