@@ -453,16 +453,28 @@ def main():
                                       "P_flip": o64["P_flip"], "P_neg": o64["P_neg"]}
         log(f"FP64: {t64:.3f} s; FP32 max |dP| = {err['max_abs_prob']:.3e}")
 
-    if a.batch_steps > 0:
-        extra["batch"] = batch_section(qw, W, torch, a.batch_steps, a.batch_single_steps)
-    if not a.no_learned:
-        extra["learned"] = learned_section(qw, W, torch)
-    if not a.no_unfused:
+    def section(name, fn):
+        # the context sections must not cost the headline line: a failure is
+        # logged and recorded in place of the section's figures
+        try:
+            extra[name] = fn()
+        except Exception as e:  # noqa: BLE001
+            log(f"{name} section failed: {e!r}")
+            extra[name] = {"error": repr(e)}
+
+    def unfused():
         u = unfused_section(qw, wl, torch)
         u["fused_ms_per_step"] = 1e3 * t32 / a.steps
         u["speedup_fused_over_unfused"] = u["ms_per_step"] / u["fused_ms_per_step"]
         u["speedup_fused_over_fft_only"] = u["fft_only_ms_per_step"] / u["fused_ms_per_step"]
-        extra["unfused_rocfft"] = u
+        return u
+
+    if a.batch_steps > 0:
+        section("batch", lambda: batch_section(qw, W, torch, a.batch_steps, a.batch_single_steps))
+    if not a.no_learned:
+        section("learned", lambda: learned_section(qw, W, torch))
+    if not a.no_unfused:
+        section("unfused_rocfft", unfused)
 
     # oracle on a bounded sample: the same grid and field, a few steps
     import oracle
