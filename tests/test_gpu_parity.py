@@ -71,6 +71,29 @@ def test_observables_match_oracle(prec):
         assert np.max(np.abs(got - ref)) <= tol, (got, ref)
 
 
+@pytest.mark.parametrize("n_max,spin0,window,ref_shift", [(0, 1, 8, 0), (1, -1, 0, 3), (2, 1, 4, -5),
+                                                          (16, -1, 8, 1)])
+def test_observables_specs_match_oracle(n_max, spin0, window, ref_shift):
+    # band windows from none to past every order the grid holds (n_max = 16:
+    # the largest accepted, 3B + 3 = 102 sums, bands beyond |n| = 8 empty),
+    # both spin references, window half-widths 0 .. k_L/dk / 2, shifted
+    # reference columns; FP64 on a seeded random state of a 256 x 64 grid
+    # (box 16 x 4 wavelengths)
+    g = W.GridSpec(nx=256, ny=64, x_min=-4.0, y_min=-1.0, lx=8.0, ly=2.0)
+    m = int(round(g.lx / W.LAMBDA_L))  # k_L / dk
+    o = W.ObsSpec(band_ref_idx=-m + ref_shift, band_half_idx=m, window_idx=min(window, m // 2), n_max=n_max,
+                  spin0=spin0)
+    print_case(test="observables_specs", n_max=n_max, spin0=spin0, window=o.window_idx, ref=o.band_ref_idx)
+    psi = W.random_state(g.ny, g.nx, seed=33)
+    ref = oracle.observables(o_grid(g), psi, o_obs(o))
+    sim = qw.Sim(g, F64)
+    sim.load(psi)
+    got = np.array(sim.observables(o))
+    sim.close()
+    assert got.shape == ref.shape == (3 * (2 * n_max + 1) + 3,)
+    assert np.max(np.abs(got - ref)) <= 1e-13, float(np.max(np.abs(got - ref)))
+
+
 SIZES = [(8, 8), (16, 8), (8, 16), (32, 64), (64, 32), (128, 8), (8, 128), (256, 16), (16, 256),
          (512, 8), (8, 512), (1024, 8), (8, 1024), (2048, 8), (8, 2048), (4096, 8), (8, 4096)]
 
