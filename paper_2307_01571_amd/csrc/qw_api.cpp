@@ -237,10 +237,15 @@ qw::ColArgs col_args(qw_ctx h, void* psi)
 // middle steps per captured chunk of the step loop
 constexpr int kGraphSteps = 64;
 
-// the step loop's device clock: 4 doubles at the end of the scalars slot
+// the step loop's device clock: 4 doubles at the end of the 256-double
+// scalars slot ([0] packet norm, [8, 8 + 3B + 3) observables, B <= 33)
+constexpr int kClockSlot = 248;
+static_assert(8 + 3 * (2 * qwh::kMaxNmax + 1) + 3 <= kClockSlot, "observables overlap the step clock");
+static_assert(kClockSlot + sizeof(qw::StepClock) / sizeof(double) <= 256, "step clock outside the scalars slot");
+
 qw::StepClock* step_clock(qw_ctx h)
 {
-    return reinterpret_cast<qw::StepClock*>(reinterpret_cast<double*>(h->ws + h->lay.scalars) + 248);
+    return reinterpret_cast<qw::StepClock*>(reinterpret_cast<double*>(h->ws + h->lay.scalars) + kClockSlot);
 }
 
 void drop_graph(qw_ctx h)
