@@ -92,6 +92,9 @@ struct qw_ctx_s {
     // state of args_version
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded on the caller's stream after the replays of each call: the
+    // executable graph is destroyed only once its last replay has finished
+    hipEvent_t exec_done = nullptr;
     const void* exec_psi = nullptr;
     unsigned long long args_version = 0, exec_version = 0;
 };
@@ -248,9 +251,16 @@ qw::StepClock* step_clock(qw_ctx h)
     return reinterpret_cast<qw::StepClock*>(reinterpret_cast<double*>(h->ws + h->lay.scalars) + kClockSlot);
 }
 
+// Destroys the captured chunk after waiting for its last replay: a caller
+// may change the beam or the state array, or destroy the context, while
+// replays it enqueued are still running, and an executable graph must not
+// be released under a running replay.
 void drop_graph(qw_ctx h)
 {
-    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->exec) {
+        if (h->exec_done) (void)hipEventSynchronize(h->exec_done);
+        (void)hipGraphExecDestroy(h->exec);
+    }
     h->exec = nullptr;
     h->exec_psi = nullptr;
 }
@@ -269,6 +279,7 @@ hipError_t ensure_graph(qw_ctx h, void* psi, qw::RowArgs r, const qw::ColArgs& c
         e = hipGetDevice(&prev);
         if (e == hipSuccess && prev != h->device) e = hipSetDevice(h->device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+        if (e == hipSuccess && !h->exec_done) e = hipEventCreateWithFlags(&h->exec_done, hipEventDisableTiming);
         if (prev != h->device) (void)hipSetDevice(prev);
         if (e != hipSuccess) return e;
     }
@@ -451,6 +462,7 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
         if (e == hipSuccess) e = ensure_graph(h, psi, r, c);
         const int64_t chunks = (n - 1) / kGraphSteps;
         for (int64_t q = 0; q < chunks && e == hipSuccess; ++q) e = hipGraphLaunch(h->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(h->exec_done, s);
         k0 += chunks * kGraphSteps;
     }
     for (int64_t k = k0; k <= n && e == hipSuccess; ++k) {
@@ -559,9 +571,12 @@ const char* qw_last_error(qw_ctx h)
 void qw_destroy(qw_ctx h)
 {
     if (!h) return;
-    drop_graph(h);
+    drop_graph(h);  // waits for the last replay
+    if (h->exec_done) (void)hipEventDestroy(h->exec_done);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     for (auto& t : h->timed) {
+        // timing brackets still pending on a stream: wait for them first
+        (void)hipEventSynchronize(t.b);
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }

@@ -239,6 +239,8 @@ struct qw_batch_s {
     // captured step-loop graph and what it was captured for
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded on the caller's stream after the replays of each call (see drop_graph)
+    hipEvent_t exec_done = nullptr;
     void* exec_psi = nullptr;
     int exec_steps = 0, exec_rw = -1, exec_cw = -1;
     bool desc_dirty = false;
@@ -274,9 +276,15 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 qw::StepClock* dev_time(qw_batch b) { return reinterpret_cast<qw::StepClock*>(b->ws + b->lay.time); }
 qw::BatchInst* dev_desc(qw_batch b) { return reinterpret_cast<qw::BatchInst*>(b->ws + b->lay.desc); }
 
+// Destroys the captured step loop after waiting for its last replay, which
+// the caller may not have waited for (a new schedule, launch shape or state
+// array, or qw_batch_destroy, can follow a qw_batch_step_n directly).
 void drop_graph(qw_batch b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->exec) {
+        if (b->exec_done) (void)hipEventSynchronize(b->exec_done);
+        (void)hipGraphExecDestroy(b->exec);
+    }
     b->exec = nullptr;
     b->exec_psi = nullptr;
 }
@@ -413,6 +421,7 @@ hipError_t ensure_graph(qw_batch b, char* psi)
     drop_graph(b);
     hipError_t e = hipSuccess;
     if (!b->cap) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess && !b->exec_done) e = hipEventCreateWithFlags(&b->exec_done, hipEventDisableTiming);
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
@@ -602,6 +611,7 @@ int qw_batch_step_n(qw_batch b, void* psi, int64_t n, double t0, double dt, void
         e = ensure_graph(b, base);
         const int64_t chunks = (n - 1) / b->graph_steps;
         for (int64_t c = 0; c < chunks && e == hipSuccess; ++c) e = hipGraphLaunch(b->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(b->exec_done, s);
         k += chunks * b->graph_steps;
     }
     for (; k < n && e == hipSuccess; ++k) e = middle_step(b, base, (int)k, false, s);
@@ -862,9 +872,11 @@ const char* qw_batch_last_error(qw_batch b)
 void qw_batch_destroy(qw_batch b)
 {
     if (!b) return;
-    drop_graph(b);
+    drop_graph(b);  // waits for the last replay
+    if (b->exec_done) (void)hipEventDestroy(b->exec_done);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (auto& t : b->timed) {
+        (void)hipEventSynchronize(t.b);  // a pending timing bracket
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
