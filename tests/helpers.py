@@ -30,3 +30,60 @@ def momenta(g: W.GridSpec):
     px = 2 * np.pi * np.fft.fftfreq(g.nx, d=g.lx / g.nx)
     py = 2 * np.pi * np.fft.fftfreq(g.ny, d=g.ly / g.ny)
     return np.meshgrid(px, py)  # arrays of shape (ny, nx)
+
+
+# ---------------------------------------------------------------------------
+# FP32 accuracy bars for the band and spin probabilities
+# ---------------------------------------------------------------------------
+# Error model of the FP32 path (state, butterflies and propagator products in
+# float; phases and sums in double), taken from GPU runs against the FP64
+# oracle and the GPU FP64 path:
+#  * The band probabilities carry an absolute error that grows linearly with
+#    the step count and is the same in size for P_0 and P_+1 (opposite in
+#    sign): float rounding of the products with the standing-wave field is
+#    correlated with the field's period, so it feeds the +-2 k_L orders
+#    coherently from step to step.  Measured: 3.5e-8 to 4.0e-8 after 1e4
+#    steps (512^2), up to 2.4e-7 after 2e4 (the 96-instance batch), 2.6e-7
+#    after 5e4 (2048^2): at most 1.2e-11 per step.
+#  * The spin-flip probability, a sum over the whole grid of projections onto
+#    the opposite spin, carries at most 2.7e-13 per step (1e-9 after 1e4
+#    steps, 5.3e-9 after 2e4 and after 5e4).
+#  * Values far above these floors show no larger error: P_+1 = 1e-3 is off
+#    by 1e-4 of itself after 2e4 steps, P_flip = 1.1e-6 by 5e-3 after 5e4.
+# The bars take three times the per-step floors plus a relative margin:
+#   |dP_n|, |dP_n^+-|, |dP_neg| <= 3.6e-11 n + 1e-3 P,
+#   |dP_flip|                   <= 1e-12 n   + 1e-2 P_flip,
+# each also within the absolute 1e-4 the FP32 form must meet.  For the
+# workloads' diffracted orders (P_+1 of 1e-5 to 1e-3) and spin flips (1e-7 to
+# 1e-6) these are bars of 1 to 6 percent of the value itself.
+FP32_ABS_BAR = 1e-4
+FP32_P_PER_STEP, FP32_P_REL = 3.6e-11, 1e-3
+FP32_FLIP_PER_STEP, FP32_FLIP_REL = 1e-12, 1e-2
+
+
+def fp32_bars(ref, n_max: int, steps: int):
+    """Per-observable FP32 bars for an observables vector [norm, P, P+, P-, P_flip, P_neg] (norm not checked)."""
+    ref = np.asarray(ref, dtype=float)
+    nb = 2 * n_max + 1
+    bars = FP32_P_PER_STEP * steps + FP32_P_REL * np.abs(ref)
+    i_flip = 1 + 3 * nb
+    bars[i_flip] = FP32_FLIP_PER_STEP * steps + FP32_FLIP_REL * abs(ref[i_flip])
+    return np.minimum(bars, FP32_ABS_BAR)
+
+
+def check_fp32_probabilities(got, ref, n_max: int, steps: int, tag: str = ""):
+    """Assert the FP32 observables against an FP64 reference, every probability
+    within fp32_bars; prints P_+1 and P_flip with their errors and bars."""
+    got = np.asarray(got, dtype=float)
+    ref = np.asarray(ref, dtype=float)
+    nb = 2 * n_max + 1
+    bars = fp32_bars(ref, n_max, steps)
+    d = np.abs(got - ref)
+    i_p1, i_flip = 1 + n_max + 1, 1 + 3 * nb
+    print(f"  {tag} P_+1 {ref[i_p1]:.4e} |d| {d[i_p1]:.2e} bar {bars[i_p1]:.2e}; "
+          f"P_flip {ref[i_flip]:.4e} |d| {d[i_flip]:.2e} bar {bars[i_flip]:.2e}; "
+          f"max |dP| {d[1:].max():.2e}", flush=True)
+    assert d[i_p1] <= bars[i_p1], ("P_+1", tag, d[i_p1], bars[i_p1])
+    assert d[i_flip] <= bars[i_flip], ("P_flip", tag, d[i_flip], bars[i_flip])
+    bad = [k for k in range(1, len(ref)) if not d[k] <= bars[k]]
+    assert not bad, [(tag, k, ref[k], d[k], bars[k]) for k in bad]

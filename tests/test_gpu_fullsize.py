@@ -9,7 +9,10 @@ References:
   * for the full 2048 x 2048, 5e4-step FP32 run: the GPU FP64 run, which the
     prefix tests tie to the oracle on the same grid.
 Bars: FP64 sampled cells within 1e-10 relative L2 and probabilities within
-1e-12 of the oracle; FP32 probabilities within 1e-4 absolute.
+1e-12 of the oracle; FP32 probabilities within 1e-4 absolute and, each on
+its own, within the FP32 error model of helpers.fp32_bars (a per-step
+floor plus a relative part; 1 to 6 percent of the diffracted-order and
+spin-flip probabilities of these runs).
 """
 import json
 import os
@@ -19,6 +22,7 @@ import pytest
 
 from paper_2307_01571_amd import qw
 from paper_2307_01571_amd import workloads as W
+from helpers import check_fp32_probabilities
 
 pytestmark = pytest.mark.gpu
 
@@ -86,7 +90,7 @@ def test_large_grid_prefix_f32_matches_oracle(name):
     sqrt(n log2 N) 2^-24.  Measured with the nearest-rounded constants:
     9.6e-6 relative L2 after 100 steps; the bar, 3e-7 n (3e-5 at 100
     steps), keeps a factor three over that.  Probabilities (ratios to the
-    current norm, which remove the drift) within 1e-6 absolute."""
+    current norm, which remove the drift): helpers.fp32_bars."""
     rec = load(name)
     wl = workload_of(rec)
     sim, obs = run_gpu(wl, qw.QW_F32, rec["steps"], rec["t0"])
@@ -97,10 +101,9 @@ def test_large_grid_prefix_f32_matches_oracle(name):
     got = np.array([psi[iy, ix] for iy, ix in cells])
     sim.close()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    d = np.max(np.abs(obs[1:] - ref_obs[1:]))
-    print(f"  FP32 sampled-cell rel L2 {err:.3e}, max |d obs| {d:.3e}")
+    print(f"  FP32 sampled-cell rel L2 {err:.3e}")
     assert err <= 3e-7 * rec["steps"]
-    assert d <= 1e-6
+    check_fp32_probabilities(obs, ref_obs, wl.obs.n_max, rec["steps"], name)
 
 
 @pytest.mark.parametrize("name", ["mid_w2", "mid_w4", "mid_w8"])
@@ -110,26 +113,25 @@ def test_mid_grid_full_run_f64_matches_oracle(name):
 
 @pytest.mark.parametrize("name", ["mid_w2", "mid_w4", "mid_w8"])
 def test_mid_grid_full_run_f32_probabilities(name):
+    """512^2, 1e4 steps, FP32 against the oracle's stored observables: every
+    probability within helpers.fp32_bars (P_+1 = 8e-8 .. 1.4e-5 and
+    P_flip = 1e-7 .. 9e-7 here; the bars are 3.6e-7 + 1e-3 P and
+    1e-8 + 1e-2 P_flip), and within 1e-4."""
     rec = load(name)
     wl = workload_of(rec)
     sim, obs = run_gpu(wl, qw.QW_F32, rec["steps"], rec["t0"])
     sim.close()
-    ref = np.array(rec["observables"])
-    d = np.abs(obs[1:] - ref[1:])
-    nb = 2 * wl.obs.n_max + 1
-    flip_rel = d[3 * nb] / max(ref[1 + 3 * nb], 1e-300)
-    print(f"  FP32 vs oracle: max |dP| {d.max():.3e}, P_+1 {ref[4]:.4e} (d {d[3]:.2e}), "
-          f"P_flip {ref[1 + 3 * nb]:.4e} (rel {flip_rel:.2e}), norm drift {obs[0] - 1:.2e}")
-    assert d.max() <= 1e-4
+    print(f"  norm drift {obs[0] - 1:.2e}")
+    check_fp32_probabilities(obs, rec["observables"], wl.obs.n_max, rec["steps"], name)
 
 
 def test_large_grid_full_run_f32_vs_f64():
-    """The throughput workload (2048^2, 5e4 steps, the launch sequence bench.py times): FP32 against the GPU FP64 run."""
+    """The throughput workload (2048^2, 5e4 steps, the launch sequence bench.py
+    times): FP32 against the GPU FP64 run, every probability within
+    helpers.fp32_bars (P_+1 = 1.1e-4 with a bar of 1.9e-6, P_flip = 1.1e-6
+    with a bar of 6e-8) and within 1e-4."""
     wl = W.large()
     _, o64 = run_gpu(wl, qw.QW_F64, wl.steps, 0.0)
     _, o32 = run_gpu(wl, qw.QW_F32, wl.steps, 0.0)
-    d = np.abs(o32[1:] - o64[1:])
-    nb = 2 * wl.obs.n_max + 1
-    print(f"  FP32 vs FP64 after {wl.steps} steps: max |dP| {d.max():.3e}; P_+1 {o64[4]:.4e} "
-          f"(d {d[3]:.2e}); P_flip {o64[1 + 3 * nb]:.4e} (d {d[3 * nb]:.2e}); norm drift {o32[0] - 1:.2e}")
-    assert d.max() <= 1e-4
+    print(f"  norm drift {o32[0] - 1:.2e}")
+    check_fp32_probabilities(o32, o64, wl.obs.n_max, wl.steps, "2048^2 5e4 steps")
