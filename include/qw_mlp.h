@@ -76,9 +76,18 @@ int qw_mlp_forward(qw_mlp h, const float *x, int32_t B, float *y, void *hip_stre
  * the targets' own units.  Default: identity. */
 int qw_mlp_set_output_map(qw_mlp h, const float *shift, const float *scale, void *hip_stream);
 
+/* Weights of the error estimate (host array of n_out floats >= 0; waits for
+ * hip_stream): qw_mlp_predict's spread is the largest over the outputs of
+ * weight x standard deviation across the nets.  Default: all one (the
+ * deviation in each output's own units).  With weights 1/scale of the
+ * output map the estimate is in the units the nets were trained in, which
+ * puts outputs of very different magnitudes on one scale. */
+int qw_mlp_set_spread_weights(qw_mlp h, const float *w, void *hip_stream);
+
 /* Ensemble prediction: mean [B][n_out] over the nets of the mapped outputs
- * and, per sample, the largest standard deviation over the outputs (the
- * error estimate), spread [B] (both device FP32). */
+ * and, per sample, the largest weighted standard deviation over the outputs
+ * (the error estimate; qw_mlp_set_spread_weights), spread [B] (both device
+ * FP32). */
 int qw_mlp_predict(qw_mlp h, const float *x, int32_t B, float *mean, float *spread, void *hip_stream);
 
 /* Loss and gradients without an update: t is [B][n_out] targets in the

@@ -40,7 +40,7 @@ struct Plan {
     int Mpad = 0;          // batch rows, padded
     std::vector<Layer> layer;
     // byte offsets
-    size_t P, Mo, V, G, Wb, Wt, shift, scale, oshift, oscale, Xb, Xt, Z, H, Ht, Y, dYb, dYt, dZb, dZt, loss_part, loss;
+    size_t P, Mo, V, G, Wb, Wt, shift, scale, oshift, oscale, swt, Xb, Xt, Z, H, Ht, Y, dYb, dYt, dZb, dZt, loss_part, loss;
     size_t Kp;             // split-K parts of the weight gradients
     int ks_max = 1;        // most K splits of a weight-gradient product
     long long kp_net = 0;  // floats per net in Kp
@@ -107,6 +107,7 @@ Plan make_plan(const qw_mlp_shape& s)
     p.scale = take(4 * kInPad);
     p.oshift = take(4 * kInPad);
     p.oscale = take(4 * kInPad);
+    p.swt = take(4 * kInPad);
     p.Xb = take(2 * M * kInPad);
     p.Xt = take(2 * M * kInPad);
     p.Z = take(4 * nets * D * M * W);
@@ -448,12 +449,13 @@ int qw_mlp_init(qw_mlp* out, const qw_mlp_shape* s, const float* shift, const fl
     h->p = p;
     h->ws = static_cast<char*>(workspace);
     hipStream_t st = as_stream(hip_stream);
-    float map[4 * kInPad] = {};
+    float map[5 * kInPad] = {};
     for (int i = 0; i < s->n_in; ++i) {
         map[i] = shift[i];
         map[kInPad + i] = scale[i];
     }
     for (int i = 0; i < kInPad; ++i) map[3 * kInPad + i] = 1.0f;  // output map: identity
+    for (int i = 0; i < kInPad; ++i) map[4 * kInPad + i] = 1.0f;  // spread weights: one
     // zero everything (the paddings of weights and activations must read as zero)
     hipError_t e = qwm::launch_fill_zero(h->ws, p.total, st);
     if (e == hipSuccess) e = hipMemcpyAsync(at<float>(h, p.shift), map, 4 * kInPad, hipMemcpyHostToDevice, st);
@@ -463,6 +465,8 @@ int qw_mlp_init(qw_mlp* out, const qw_mlp_shape* s, const float* shift, const fl
         e = hipMemcpyAsync(at<float>(h, p.oshift), map + 2 * kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(at<float>(h, p.oscale), map + 3 * kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<float>(h, p.swt), map + 4 * kInPad, 4 * kInPad, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         mfail(nullptr, QW_E_DEVICE, "network set-up: %s", hipGetErrorString(e));
@@ -510,6 +514,22 @@ int qw_mlp_set_output_map(qw_mlp h, const float* shift, const float* scale, void
     return QW_OK;
 }
 
+int qw_mlp_set_spread_weights(qw_mlp h, const float* w, void* hip_stream)
+{
+    if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
+    if (!w) return mfail(h, QW_E_ARG, "weights are NULL");
+    float buf[kInPad] = {};
+    for (int i = 0; i < h->p.s.n_out; ++i) {
+        if (!std::isfinite(w[i]) || w[i] < 0.0f) return mfail(h, QW_E_ARG, "spread weight %d is not finite and >= 0", i);
+        buf[i] = w[i];
+    }
+    hipStream_t st = as_stream(hip_stream);
+    hipError_t e = hipMemcpyAsync(at<float>(h, h->p.swt), buf, 4 * kInPad, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return mhip(h, e, "spread weights");
+    return QW_OK;
+}
+
 int qw_mlp_get_params(qw_mlp h, float* params, void* hip_stream)
 {
     if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
@@ -550,7 +570,8 @@ int qw_mlp_predict(qw_mlp h, const float* x, int32_t B, float* mean, float* spre
     hipError_t e = forward(h, x, nullptr, B, s);
     if (e == hipSuccess)
         e = qwm::launch_ensemble(at<float>(h, p.Y), (long long)p.Mpad * kInPad, kInPad, B, p.s.n_out, p.s.n_nets,
-                                 at<float>(h, p.oshift), at<float>(h, p.oscale), mean, spread, s);
+                                 at<float>(h, p.oshift), at<float>(h, p.oscale), at<float>(h, p.swt), mean, spread,
+                                 s);
     if (e != hipSuccess) return mhip(h, e, "predict");
     return QW_OK;
 }

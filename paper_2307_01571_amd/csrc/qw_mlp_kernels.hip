@@ -213,10 +213,12 @@ __global__ void loss_finish(const float* part, long long s_part, int n_part, flo
     }
 }
 
-// ensemble mean and spread (largest standard deviation over the outputs) of
-// the mapped outputs y oscale + oshift
+// ensemble mean and spread of the mapped outputs y oscale + oshift: the
+// spread is the largest over the outputs of the standard deviation across
+// the nets times the output's weight swt
 __global__ __launch_bounds__(256) void ensemble(const float* y, long long s_net, int ld, int B, int n_out, int nets,
-                                                const float* oshift, const float* oscale, float* mean, float* spread)
+                                                const float* oshift, const float* oscale, const float* swt,
+                                                float* mean, float* spread)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= B) return;
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void ensemble(const float* y, long long s_net,
             q += d * d;
         }
         mean[(size_t)m * n_out + o] = mu;
-        const float sd = nets > 1 ? sqrtf(q / (nets - 1)) : 0.0f;
+        const float sd = (nets > 1 ? sqrtf(q / (nets - 1)) : 0.0f) * swt[o];
         worst = sd > worst ? sd : worst;
     }
     spread[m] = worst;
@@ -318,10 +320,10 @@ hipError_t launch_loss_finish(const float* part, long long s_part, int n_part, f
 }
 
 hipError_t launch_ensemble(const float* y, long long s_net, int ld, int B, int n_out, int nets, const float* oshift,
-                           const float* oscale, float* mean, float* spread, hipStream_t s)
+                           const float* oscale, const float* swt, float* mean, float* spread, hipStream_t s)
 {
     hipLaunchKernelGGL(ensemble, dim3((B + 255) / 256), dim3(256), 0, s, y, s_net, ld, B, n_out, nets, oshift, oscale,
-                       mean, spread);
+                       swt, mean, spread);
     return hipGetLastError();
 }
 

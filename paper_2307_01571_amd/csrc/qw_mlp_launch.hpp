@@ -92,6 +92,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_loss_finish(const float* part, long long s_part, int n_part, float inv_count, float* loss,
                               int nets, hipStream_t s);
 hipError_t launch_ensemble(const float* y, long long s_net, int ld, int B, int n_out, int nets, const float* oshift,
-                           const float* oscale, float* mean, float* spread, hipStream_t s);
+                           const float* oscale, const float* swt, float* mean, float* spread, hipStream_t s);
 
 }  // namespace qwm

@@ -40,7 +40,7 @@ EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_set_frame",
             "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
             "qw_batch_destroy",
             "qw_mlp_param_count", "qw_mlp_workspace_bytes", "qw_mlp_init", "qw_mlp_set_params",
-            "qw_mlp_set_output_map", "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_gradients", "qw_mlp_train_step",
+            "qw_mlp_set_output_map", "qw_mlp_set_spread_weights", "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_gradients", "qw_mlp_train_step",
             "qw_gemm_bf16_nt", "qw_mlp_last_error", "qw_mlp_destroy")
 _NO_STATUS = ("qw_last_error", "qw_destroy", "qw_batch_last_error", "qw_batch_destroy", "qw_mlp_last_error",
               "qw_mlp_destroy")
@@ -139,6 +139,7 @@ def lib():
     L.qw_mlp_set_params.argtypes = [vp, vp, vp]
     L.qw_mlp_get_params.argtypes = [vp, vp, vp]
     L.qw_mlp_set_output_map.argtypes = [vp, fp, fp, vp]
+    L.qw_mlp_set_spread_weights.argtypes = [vp, fp, vp]
     L.qw_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     L.qw_mlp_predict.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.qw_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp]
@@ -373,6 +374,11 @@ def qw_mlp_set_output_map(h: int, shift, scale, n_out: int, stream: int) -> None
     sh = (ctypes.c_float * n_out)(*[float(v) for v in shift])
     sc = (ctypes.c_float * n_out)(*[float(v) for v in scale])
     _mcheck(lib().qw_mlp_set_output_map(_p(h), sh, sc, _p(stream)), h)
+
+
+def qw_mlp_set_spread_weights(h: int, w, n_out: int, stream: int) -> None:
+    wa = (ctypes.c_float * n_out)(*[float(v) for v in w])
+    _mcheck(lib().qw_mlp_set_spread_weights(_p(h), wa, _p(stream)), h)
 
 
 def qw_mlp_get_params(h: int, params_ptr: int, stream: int) -> None:
@@ -611,6 +617,10 @@ class MLP:
 
     def set_output_map(self, shift, scale) -> None:
         qw_mlp_set_output_map(self.h, shift, scale, self.shape.n_out, self.stream())
+
+    def set_spread_weights(self, w) -> None:
+        """Per-output weights of the ensemble spread predict() returns (default all one)."""
+        qw_mlp_set_spread_weights(self.h, w, self.shape.n_out, self.stream())
 
     def params(self):
         out = self.torch.empty(self.shape.n_nets * self.per_net, dtype=self.torch.float32, device=self.device)

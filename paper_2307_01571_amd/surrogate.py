@@ -14,8 +14,20 @@ probabilities P_0, P_+1, P_-1, P_+2, P_-2 and P_flip the solver reports
 * ``evaluate``: held-out runs (never seen in training) -> error of the
   ensemble mean against the solver, the ensemble spread as error estimate,
   the share of queries the fallback would send to the solver.
-* ``SurrogateWithFallback``: answers from the network where the spread is at
-  most ``tol`` and from the solver elsewhere.
+* ``SurrogateWithFallback``: answers from the network where the error
+  estimate is at most ``tol`` and from the solver elsewhere.
+
+The error estimate is the ensemble spread in standardised units: for each
+output the standard deviation of the four nets' predictions divided by that
+output's standard deviation over the training targets, the largest of the
+six.  The outputs span 1e-12 to 1, so a spread in the outputs' own units
+would let the small ones (P_+-2, P_flip) through whatever their error
+(measured: an absolute 1e-2 sends no in-distribution query to the solver).
+The default tolerance, 0.1 of each output's spread of values, sits above
+the nets' typical disagreement on held-out runs (0.02 to 0.07) and below
+that of the queries they get wrong; it also implies the absolute 1e-2 on
+every output whose training spread is below 0.1 (all six here; train()
+checks it), so it is the stricter of the two readings.
 
 Torch serves as device memory and for shuffling minibatches; the network's
 arithmetic runs in the library's kernels, the solver's in its own.
@@ -39,6 +51,8 @@ from . import workloads as W
 N_GRID = 512
 STEPS = 20_000
 SNAP_EVERY = 1000
+FALLBACK_TOL = 0.1  # error estimate (standardised units) above which the solver answers
+ABS_TOL = 1e-2      # the absolute probability tolerance the standardised one implies
 
 
 def _log(*a):
@@ -145,6 +159,10 @@ def train(x, y, epochs: int = 200, batch: int = 4096, lr: float = 1e-3, lr_end: 
     batch = min(batch, n)
     net = net or make_net(max_batch=max(batch, 4096), seed=seed)
     net.set_output_map(mu, sd)
+    net.set_spread_weights(1.0 / sd)  # the error estimate in standardised units
+    if np.any(sd * FALLBACK_TOL > ABS_TOL):
+        _log(f"note: an output's spread of values ({sd.max():.3g}) makes the standardised tolerance "
+             f"looser than {ABS_TOL} absolute")
     net.target_mean, net.target_std = mu, sd
     g = torch.Generator(device="cpu").manual_seed(seed)
     loss = torch.zeros(W.SURROGATE_SHAPE["n_nets"], device=dev)
@@ -182,9 +200,10 @@ def predict(net, x):
 
 
 class SurrogateWithFallback:
-    """Network answers where the ensemble spread is <= tol, the solver's elsewhere."""
+    """Network answers where the error estimate (ensemble spread in
+    standardised units) is <= tol, the solver's elsewhere."""
 
-    def __init__(self, net, tol: float = 1e-2):
+    def __init__(self, net, tol: float = FALLBACK_TOL):
         self.net = net
         self.tol = tol
 
@@ -197,15 +216,18 @@ class SurrogateWithFallback:
         return out, use, spread
 
 
-def evaluate(net, x, y, tol: float = 1e-2) -> dict:
-    """Errors of the ensemble mean against the solver.  Besides absolute
-    errors (the fallback tolerance is absolute), each output's RMS error is
-    given relative to its spread over the evaluated set and to the RMS error
-    of the constant predictor (the training mean): skill = 1 - (rmse /
-    rmse_constant)^2."""
+def evaluate(net, x, y, tol: float = FALLBACK_TOL) -> dict:
+    """Errors of the ensemble mean against the solver: absolute, and in
+    standardised units (each output's error over its training standard
+    deviation, the units of the error estimate); each output's RMS error
+    relative to its spread over the evaluated set and to the RMS error of the
+    constant predictor (the training mean): skill = 1 - (rmse /
+    rmse_constant)^2; and how the fallback at tol splits the queries."""
     mean, spread = predict(net, x)
     err = np.abs(mean - y)
-    worst = err.max(axis=1)
+    sd = getattr(net, "target_std", np.ones(err.shape[1]))
+    err_std = err / sd
+    worst = err_std.max(axis=1)
     accept = spread <= tol
     rmse = np.sqrt(np.mean((mean - y) ** 2, axis=0))
     mu = getattr(net, "target_mean", np.mean(y, axis=0))
@@ -215,9 +237,12 @@ def evaluate(net, x, y, tol: float = 1e-2) -> dict:
            "skill_vs_constant": (1 - (rmse / np.maximum(rmse0, 1e-300)) ** 2).tolist(),
            "mae": err.mean(axis=0).tolist(), "max_abs": err.max(axis=0).tolist(),
            "max_abs_rel_to_output_max": (err.max(axis=0) / np.maximum(np.abs(y).max(axis=0), 1e-300)).tolist(),
-           "max_abs_all": float(worst.max()), "share_within_tol": float(np.mean(worst <= tol)),
+           "max_abs_all": float(err.max()), "max_std_all": float(worst.max()),
+           "share_within_tol": float(np.mean(worst <= tol)),
            "fallback_share": float(1 - accept.mean()),
-           "max_abs_accepted": float(worst[accept].max()) if accept.any() else None,
+           "mean_std_err_accepted": float(worst[accept].mean()) if accept.any() else None,
+           "mean_std_err_fallback": float(worst[~accept].mean()) if (~accept).any() else None,
+           "max_std_err_accepted": float(worst[accept].max()) if accept.any() else None,
            "accepted_within_tol": float(np.mean(worst[accept] <= tol)) if accept.any() else None,
            "spread_vs_error_corr": float(np.corrcoef(spread, worst)[0, 1]) if len(x) > 2 else None}
     return res

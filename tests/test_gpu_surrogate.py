@@ -4,8 +4,9 @@ the ensemble trained by the library's kernels, and the fallback policy.
 * every generated sample is exactly the single-instance solver's answer for
   its parameters and time (same kernels, same reduction order: 1e-12);
 * a network trained on held-in runs predicts held-out runs, its queries are
-  more than 100 times faster than one solve, and every query the policy
-  sends to the solver returns the solver's own answer.
+  more than 100 times faster than one solve, the fallback sends the queries
+  it is unsure of to the solver, and every such query returns the solver's
+  own answer.
 """
 import time
 
@@ -46,23 +47,41 @@ def test_generated_samples_are_the_solver_answers():
 
 @pytest.mark.timeout(600)
 def test_trained_surrogate_with_fallback():
+    """Train on 56 runs (560 samples), test on 8 held-out runs.
+
+    Bars, from the standardised loss (1 = the constant predictor):
+      * training loss below 0.1 of its start.  300 epochs of two minibatches
+        (600 Adam steps) stop at 0.099 -- too few steps, not a plateau: the
+        loss falls to 5e-3 after 1000 epochs and to 1.6e-3 after 2000, the
+        count used here;
+      * held-out skill above 0.9 on every output (measured 0.979 to 0.9994
+        after 2000 epochs) and the largest held-out error below 1 standard
+        deviation of its output (measured 0.40);
+      * the fallback: queries at A0 = 3 (never seen; spread 12 to 34 in
+        standardised units) go to the solver, and so does a share of the
+        held-out queries, whose mean error is larger than that of the
+        queries the network answers (the spread is informative).
+    """
     print("[case] surrogate_train runs=64 n=512 steps=2000", flush=True)
     x, y, rid = S.generate(64, seed=3, steps=2000, snap_every=200, n=512)
     held = rid >= 56
-    net, hist = S.train(x[~held], y[~held], epochs=300, batch=256, lr=2e-3)
-    assert hist[-1] < 0.5 * hist[0]  # standardised units: 1 = the constant predictor
+    net, hist = S.train(x[~held], y[~held], epochs=2000, batch=256, lr=2e-3)
+    print(f"  loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    assert hist[-1] < 0.1 * hist[0]
     ev = S.evaluate(net, x[held], y[held])
     print("  held-out:", ev)
-    assert ev["max_abs_all"] < 0.2
-    # better than the constant predictor on the leading outputs
-    assert ev["skill_vs_constant"][0] > 0.5 and ev["skill_vs_constant"][1] > 0.5
-    pol = S.SurrogateWithFallback(net, tol=1e-2)
+    assert min(ev["skill_vs_constant"]) > 0.9
+    assert ev["max_std_all"] < 1.0
+    assert 0.0 < ev["fallback_share"] < 0.5
+    assert ev["mean_std_err_fallback"] > ev["mean_std_err_accepted"]
+    pol = S.SurrogateWithFallback(net)
     # queries inside and far outside the training ranges (A0 = 3 was never seen)
     q = np.concatenate([x[held][:6], x[held][:2] * np.array([1, 0, 1, 1, 1]) + np.array([0, 3.0, 0, 0, 0])])
     out, used, spread = pol(q)
+    print("  fallback used:", used, "spread:", spread)
+    assert used[-2:].all()
     ref = S.solve(q)
     assert np.all(np.abs(out[used] - ref[used]) == 0)
-    print("  fallback used:", used, "spread:", spread)
     lat = S.latency(net, x[held][:4], reps=5)
     print("  latency:", lat)
     assert lat["speedup_1_query"] > 100
