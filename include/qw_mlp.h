@@ -90,6 +90,21 @@ int qw_mlp_set_spread_weights(qw_mlp h, const float *w, void *hip_stream);
  * FP32). */
 int qw_mlp_predict(qw_mlp h, const float *x, int32_t B, float *mean, float *spread, void *hip_stream);
 
+/* qw_mlp_predict for callers that cannot allocate or pass scratch memory
+ * (code under HIP graph capture, serving loops): the same results, with the
+ * inputs and activations of the prediction in a static device array of the
+ * library (QW_MLP_STATIC_SCRATCH_BYTES per GPU, held until the process ends,
+ * set up by qw_mlp_init) instead of the network's workspace.  Allocates
+ * nothing.  B <= QW_MLP_STATIC_MAX_BATCH, and the network's activations for
+ * B rows must fit the array (4 nets of depth 4 and width 256: up to 256
+ * rows); otherwise QW_E_SIZE before anything is enqueued.  All calls on one
+ * GPU share the array: two such calls that overlap on a GPU (other streams,
+ * other networks, other host threads) race and must be serialised by the
+ * caller. */
+#define QW_MLP_STATIC_MAX_BATCH 256
+#define QW_MLP_STATIC_SCRATCH_BYTES (4u << 20)
+int qw_mlp_predict_static(qw_mlp h, const float *x, int32_t B, float *mean, float *spread, void *hip_stream);
+
 /* Loss and gradients without an update: t is [B][n_out] targets in the
  * units of the raw outputs (standardised, if an output map is used); grads is
  * laid out as the parameters (n_nets x per_net FP32), loss is [n_nets]

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,15 @@
 #include "qw_mlp.h"
 #include "qw_host.hpp"
 #include "qw_mlp_launch.hpp"
+
+// Scratch of qw_mlp_predict_static: the inputs and activations of one
+// prediction, in a device array of the library rather than the caller's
+// workspace (each GPU the library runs on holds its own copy until the
+// process ends).  Host code must not pass `scratch` itself to a kernel (on
+// the host it names a stand-in, not device memory): it uses the address
+// hipGetSymbolAddress gives for the device, kept per device below.
+constexpr size_t kScratchBytes = (size_t)QW_MLP_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -139,6 +149,7 @@ Plan make_plan(const qw_mlp_shape& s)
 struct qw_mlp_s {
     Plan p;
     char* ws = nullptr;
+    int device = 0;   // the workspace's device
     long long t = 0;  // Adam steps taken
     std::string err;
 };
@@ -202,25 +213,62 @@ qwm::AdamArgs adam_args(qw_mlp h, int update, float lr)
 // Forward pass of every net for B samples.  With t (targets) the training
 // outputs are kept: pre-activations, transposed activations, dY and the loss
 // partials.
-hipError_t forward(qw_mlp h, const float* x, const float* t, int B, hipStream_t s)
+// Where a forward pass keeps its inputs and activations: the workspace's
+// buffers (rows M = the padded maximum batch), or the static scratch array
+// of qw_mlp_predict_static (rows M = its padded batch).
+struct Act {
+    __bf16 *Xb, *Xt, *H;
+    float* Y;
+    int M;
+};
+
+Act ws_act(qw_mlp h)
 {
     const Plan& p = h->p;
-    const int W = p.s.width, D = p.s.depth, M = p.Mpad, nets = p.s.n_nets;
+    return {at<__bf16>(h, p.Xb), at<__bf16>(h, p.Xt), at<__bf16>(h, p.H), at<float>(h, p.Y), p.Mpad};
+}
+
+// bytes of the activation buffers for M rows, each region 256-aligned, and their offsets
+struct ActLayout {
+    size_t xb, xt, hh, y, total;
+};
+ActLayout act_layout(const Plan& p, int M)
+{
+    const size_t nets = p.s.n_nets, W = p.s.width, D = p.s.depth;
+    ActLayout a{};
+    size_t o = 0;
+    a.xb = o;
+    o = align_up(o + 2 * (size_t)M * kInPad);
+    a.xt = o;
+    o = align_up(o + 2 * (size_t)M * kInPad);
+    a.hh = o;
+    o = align_up(o + 2 * nets * D * M * W);
+    a.y = o;
+    o = align_up(o + 4 * nets * M * kInPad);
+    a.total = o;
+    return a;
+}
+
+// training (t != NULL) needs the workspace's activations (a.M == Mpad)
+hipError_t forward(qw_mlp h, const Act& a, const float* x, const float* t, int B, hipStream_t s)
+{
+    const Plan& p = h->p;
+    const int W = p.s.width, D = p.s.depth, M = a.M, nets = p.s.n_nets;
     const int Mp = round64(B);
     const bool train = t != nullptr;
-    hipError_t e = qwm::launch_prep_input(x, B, p.s.n_in, Mp, at<float>(h, p.shift), at<float>(h, p.scale),
-                                          at<__bf16>(h, p.Xb), at<__bf16>(h, p.Xt), s);
+    hipError_t e = qwm::launch_prep_input(x, B, p.s.n_in, Mp, at<float>(h, p.shift), at<float>(h, p.scale), a.Xb,
+                                          a.Xt, s);
     // note: Xt rows are Mp long here (ld = Mp); the products below read them with ld = Mp
     const long long sAct = (long long)D * M * W;  // per-net stride of Z, H, Ht
     for (int l = 0; l < D && e == hipSuccess; ++l) {
         const Layer& y = p.layer[l];
         qwm::GemmArgs g{};
         if (l == 0) {
-            g.A = at<__bf16>(h, p.Xb);
+            g.A = a.Xb;
             g.sA = 0;
             g.lda = kInPad;
         } else {
-            g.A = at<__bf16>(h, p.H) + (size_t)(l - 1) * M * W;
+            g.A = a.H + (size_t)(l - 1) * M * W;
             g.sA = sAct;
             g.lda = W;
         }
@@ -242,7 +290,7 @@ hipError_t forward(qw_mlp h, const float* x, const float* t, int B, hipStream_t 
             g.ldct = Mp;
             g.nct = W;
         }
-        g.Cb = at<__bf16>(h, p.H) + (size_t)l * M * W;
+        g.Cb = a.H + (size_t)l * M * W;
         g.sCb = sAct;
         g.ldcb = W;
         e = qwm::launch_gemm(qwm::EPI_HIDDEN, g, nets, W, s);
@@ -250,7 +298,7 @@ hipError_t forward(qw_mlp h, const float* x, const float* t, int B, hipStream_t 
     if (e != hipSuccess) return e;
     const Layer& y = p.layer[D];
     qwm::GemmArgs g{};
-    g.A = at<__bf16>(h, p.H) + (size_t)(D - 1) * M * W;
+    g.A = a.H + (size_t)(D - 1) * M * W;
     g.sA = sAct;
     g.lda = W;
     g.B = at<__bf16>(h, p.Wb) + y.wb_off;
@@ -262,7 +310,7 @@ hipError_t forward(qw_mlp h, const float* x, const float* t, int B, hipStream_t 
     g.Mpad = Mp;
     g.bias = at<float>(h, p.P) + y.b_off;
     g.sbias = p.np;
-    g.Cf = at<float>(h, p.Y);
+    g.Cf = a.Y;
     g.sCf = (long long)M * kInPad;
     g.ldcf = kInPad;
     if (train) {
@@ -388,6 +436,35 @@ hipError_t backward(qw_mlp h, int B, hipStream_t s)
     return e;
 }
 
+// per-device addresses of `scratch`, looked up once per device with that
+// device current (qw_mlp_init), read by qw_mlp_predict_static
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != device) e = hipSetDevice(device);
+    void* ptr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e == hipSuccess && !ptr) e = hipErrorInvalidSymbol;
+    if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+    return e;
+}
+
+void* scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 int check_batch(qw_mlp h, const float* x, int B)
 {
     if (!h) return mfail(nullptr, QW_E_ARG, "network is NULL");
@@ -444,10 +521,16 @@ int qw_mlp_init(qw_mlp* out, const qw_mlp_shape* s, const float* shift, const fl
         const int drc = qwh::device_of(workspace, &ws_device, &msg);
         if (drc != QW_OK) return mfail(nullptr, drc, "%s", msg.c_str());
     }
+    {
+        const hipError_t se = scratch_setup(ws_device);
+        if (se != hipSuccess)
+            return mfail(nullptr, QW_E_DEVICE, "static scratch of device %d: %s", ws_device, hipGetErrorString(se));
+    }
     qw_mlp h = new (std::nothrow) qw_mlp_s;
     if (!h) return mfail(nullptr, QW_E_DEVICE, "out of host memory");
     h->p = p;
     h->ws = static_cast<char*>(workspace);
+    h->device = ws_device;
     hipStream_t st = as_stream(hip_stream);
     float map[5 * kInPad] = {};
     for (int i = 0; i < s->n_in; ++i) {
@@ -547,7 +630,7 @@ int qw_mlp_forward(qw_mlp h, const float* x, int32_t B, float* y, void* hip_stre
     if (!y) return mfail(h, QW_E_ARG, "y is NULL");
     hipStream_t s = as_stream(hip_stream);
     const Plan& p = h->p;
-    hipError_t e = forward(h, x, nullptr, B, s);
+    hipError_t e = forward(h, ws_act(h), x, nullptr, B, s);
     // compact [net][B][n_out] from the padded [net][Mpad][16]
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(y, sizeof(float) * p.s.n_out, at<float>(h, p.Y), sizeof(float) * kInPad,
@@ -567,12 +650,40 @@ int qw_mlp_predict(qw_mlp h, const float* x, int32_t B, float* mean, float* spre
     if (!mean || !spread) return mfail(h, QW_E_ARG, "mean or spread is NULL");
     hipStream_t s = as_stream(hip_stream);
     const Plan& p = h->p;
-    hipError_t e = forward(h, x, nullptr, B, s);
+    hipError_t e = forward(h, ws_act(h), x, nullptr, B, s);
     if (e == hipSuccess)
         e = qwm::launch_ensemble(at<float>(h, p.Y), (long long)p.Mpad * kInPad, kInPad, B, p.s.n_out, p.s.n_nets,
                                  at<float>(h, p.oshift), at<float>(h, p.oscale), at<float>(h, p.swt), mean, spread,
                                  s);
     if (e != hipSuccess) return mhip(h, e, "predict");
+    return QW_OK;
+}
+
+int qw_mlp_predict_static(qw_mlp h, const float* x, int32_t B, float* mean, float* spread, void* hip_stream)
+{
+    int rc = check_batch(h, x, B);
+    if (rc != QW_OK) return rc;
+    if (!mean || !spread) return mfail(h, QW_E_ARG, "mean or spread is NULL");
+    if (B > QW_MLP_STATIC_MAX_BATCH)
+        return mfail(h, QW_E_SIZE, "batch %d exceeds the static path's maximum of %d", B, QW_MLP_STATIC_MAX_BATCH);
+    const Plan& p = h->p;
+    const int M = round64(B);
+    const ActLayout L = act_layout(p, M);
+    if (L.total > kScratchBytes)
+        return mfail(h, QW_E_SIZE, "a batch of %d of this network needs %zu bytes of scratch, the static array has %zu",
+                     B, L.total, kScratchBytes);
+    char* base = static_cast<char*>(scratch_of(h->device));
+    if (!base) return mfail(h, QW_E_STATE, "static scratch of device %d was not set up", h->device);
+    // every region is written before it is read (inputs zero-padded by the
+    // input kernel, activations and outputs by the products): nothing to clear
+    const Act a{reinterpret_cast<__bf16*>(base + L.xb), reinterpret_cast<__bf16*>(base + L.xt),
+                reinterpret_cast<__bf16*>(base + L.hh), reinterpret_cast<float*>(base + L.y), M};
+    hipStream_t s = as_stream(hip_stream);
+    hipError_t e = forward(h, a, x, nullptr, B, s);
+    if (e == hipSuccess)
+        e = qwm::launch_ensemble(a.Y, (long long)M * kInPad, kInPad, B, p.s.n_out, p.s.n_nets, at<float>(h, p.oshift),
+                                 at<float>(h, p.oscale), at<float>(h, p.swt), mean, spread, s);
+    if (e != hipSuccess) return mhip(h, e, "predict (static scratch)");
     return QW_OK;
 }
 
@@ -584,7 +695,7 @@ int qw_mlp_gradients(qw_mlp h, const float* x, const float* t, int32_t B, float*
     if (!t) return mfail(h, QW_E_ARG, "t is NULL");
     hipStream_t s = as_stream(hip_stream);
     const Plan& p = h->p;
-    hipError_t e = forward(h, x, t, B, s);
+    hipError_t e = forward(h, ws_act(h), x, t, B, s);
     if (e == hipSuccess) e = backward(h, B, s);
     if (e == hipSuccess && grads)
         e = hipMemcpyAsync(grads, at<float>(h, p.G), 4 * (size_t)p.s.n_nets * p.np, hipMemcpyDeviceToDevice, s);
@@ -602,7 +713,7 @@ int qw_mlp_train_step(qw_mlp h, const float* x, const float* t, int32_t B, float
     if (!std::isfinite(lr) || lr < 0) return mfail(h, QW_E_ARG, "learning rate must be finite and >= 0");
     hipStream_t s = as_stream(hip_stream);
     const Plan& p = h->p;
-    hipError_t e = forward(h, x, t, B, s);
+    hipError_t e = forward(h, ws_act(h), x, t, B, s);
     if (e == hipSuccess) e = backward(h, B, s);
     h->t += 1;
     if (e == hipSuccess) e = qwm::launch_adam(adam_args(h, 1, lr), p.s.n_nets, s);

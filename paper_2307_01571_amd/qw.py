@@ -27,6 +27,7 @@ QW_E_STATE = -6
 
 QW_F64 = 0
 QW_F32 = 1
+QW_MLP_STATIC_MAX_BATCH = 256  # qw_mlp.h
 
 QW_BEAM_NONE = 0
 QW_BEAM_STANDING_PARAXIAL = 1
@@ -40,7 +41,8 @@ EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_set_frame",
             "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
             "qw_batch_destroy",
             "qw_mlp_param_count", "qw_mlp_workspace_bytes", "qw_mlp_init", "qw_mlp_set_params",
-            "qw_mlp_set_output_map", "qw_mlp_set_spread_weights", "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_gradients", "qw_mlp_train_step",
+            "qw_mlp_set_output_map", "qw_mlp_set_spread_weights", "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_predict_static",
+            "qw_mlp_gradients", "qw_mlp_train_step",
             "qw_gemm_bf16_nt", "qw_mlp_last_error", "qw_mlp_destroy")
 _NO_STATUS = ("qw_last_error", "qw_destroy", "qw_batch_last_error", "qw_batch_destroy", "qw_mlp_last_error",
               "qw_mlp_destroy")
@@ -142,6 +144,7 @@ def lib():
     L.qw_mlp_set_spread_weights.argtypes = [vp, fp, vp]
     L.qw_mlp_forward.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     L.qw_mlp_predict.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
+    L.qw_mlp_predict_static.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.qw_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp]
     L.qw_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp]
     L.qw_gemm_bf16_nt.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32,
@@ -391,6 +394,10 @@ def qw_mlp_forward(h: int, x_ptr: int, B: int, y_ptr: int, stream: int) -> None:
 
 def qw_mlp_predict(h: int, x_ptr: int, B: int, mean_ptr: int, spread_ptr: int, stream: int) -> None:
     _mcheck(lib().qw_mlp_predict(_p(h), _p(x_ptr), int(B), _p(mean_ptr), _p(spread_ptr), _p(stream)), h)
+
+
+def qw_mlp_predict_static(h: int, x_ptr: int, B: int, mean_ptr: int, spread_ptr: int, stream: int) -> None:
+    _mcheck(lib().qw_mlp_predict_static(_p(h), _p(x_ptr), int(B), _p(mean_ptr), _p(spread_ptr), _p(stream)), h)
 
 
 def qw_mlp_gradients(h: int, x_ptr: int, t_ptr: int, B: int, grads_ptr, loss_ptr, stream: int) -> None:
