@@ -88,8 +88,8 @@ struct qw_ctx_s {
     bool timing = false;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
-    // the step loop's captured chunk: valid for exec_psi and the beam/frame
-    // state of args_version
+    // the step loop's captured chunk (it works on the workspace plane): valid
+    // for exec_psi and the beam/frame state of args_version
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
     // recorded on the caller's stream after the replays of each call: the
@@ -267,8 +267,8 @@ void drop_graph(qw_ctx h)
 
 // One chunk of kGraphSteps middle steps (column pass, then the row pass
 // V(t_k, dt) with k read from the device clock) and the clock's advance,
-// captured on the library's own stream; recaptured when psi, the beam or
-// the frame change.  r and c are the step loop's argument blocks.
+// captured on the library's own stream; recaptured when the state array it
+// works on (the workspace plane), the beam or the frame change.  r and c are the step loop's argument blocks.
 hipError_t ensure_graph(qw_ctx h, void* psi, qw::RowArgs r, const qw::ColArgs& c)
 {
     if (h->exec && h->exec_psi == psi && h->exec_version == h->args_version) return hipSuccess;
@@ -422,6 +422,12 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
     if (!psi) return fail(h, QW_E_ARG, "psi is NULL");
     if (n < 0) return fail(h, QW_E_ARG, "n = %lld is negative", (long long)n);
+    {
+        // the propagation runs through the workspace plane: psi must not overlap the workspace
+        const char* p = static_cast<const char*>(psi);
+        const size_t state = (size_t)h->g.nx * h->g.ny * 4 * (f32(h) ? 8 : 16);
+        if (p < h->ws + h->ws_bytes && p + state > h->ws) return fail(h, QW_E_ARG, "psi overlaps the workspace");
+    }
     if (!qwh::finite_all({t0, dt})) return fail(h, QW_E_ARG, "t0 and dt must be finite");
     if (!h->beam_set) return fail(h, QW_E_STATE, "qw_set_beam has not been called");
     if (n == 0) return QW_OK;
@@ -436,16 +442,25 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     int rc = ensure_tables(h, s);
     if (rc == QW_OK) rc = ensure_kinetic_table(h, dt, s);
     if (rc != QW_OK) return rc;
-    qw::RowArgs r = row_args(h, psi, psi);
+    // Between its first and last row pass a propagation keeps the state in
+    // the workspace plane, in the split layout of the middle passes: the first
+    // row pass reads psi and writes the plane, the last reads the plane and
+    // writes psi.
+    void* plane = h->ws + h->lay.plane;
+    qw::RowArgs r = row_args(h, plane, plane);
     r.t0 = t0;
     r.dt = dt;
-    qw::ColArgs c = col_args(h, psi);
+    qw::ColArgs c = col_args(h, plane);
     c.dt = dt;
     hipError_t e;
     // V(t0, dt/2) then F_x
     r.k = 0;
     r.tau_frac = 0.5;
-    e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_FIRST, r, s); });
+    {
+        qw::RowArgs f = r;
+        f.src = psi;
+        e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_FIRST, f, s); });
+    }
     int64_t k0 = 1;
     // a caller capturing its own stream (or a stream whose state cannot be
     // queried) gets the plain launches
@@ -459,7 +474,7 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
         // middle steps 1 .. chunks kGraphSteps as replays of one captured chunk
         qw::StepClock* clk = step_clock(h);
         e = qw::launch_clock_set(clk, t0, dt, 1, s);
-        if (e == hipSuccess) e = ensure_graph(h, psi, r, c);
+        if (e == hipSuccess) e = ensure_graph(h, plane, r, c);
         const int64_t chunks = (n - 1) / kGraphSteps;
         for (int64_t q = 0; q < chunks && e == hipSuccess; ++q) e = hipGraphLaunch(h->exec, s);
         if (e == hipSuccess) e = hipEventRecord(h->exec_done, s);
@@ -474,6 +489,7 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
             e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_MID, r, s); });
         } else {
             r.tau_frac = 0.5;
+            r.dst = psi;
             e = timed(h, 0, s, [&] { return launch_row(h, qw::ROW_LAST, r, s); });
         }
     }

@@ -12,7 +12,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// No implicit contraction of a * b + c into fused multiply-adds in the
+// kernels: where a fused operation is wanted it is written out (fmx below).
+// The rounding of every result then follows the source alone, so kernels
+// that run the same arithmetic in different tile shapes or state layouts
+// (single-instance and batched passes) produce identical bits.
+#pragma clang fp contract(off)
+
 namespace qw {
+
+__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename T>
 struct cx {
@@ -28,7 +38,7 @@ __device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return {a.re - b.re, a.
 template <typename T>
 __device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b)
 {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fmx(a.re, b.re, -(a.im * b.im)), fmx(a.re, b.im, a.im * b.re)};
 }
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
@@ -95,7 +105,12 @@ __device__ __forceinline__ void bload2(cx<double>*, __amdgpu_buffer_rsrc_t r, ui
 __device__ __forceinline__ void bstore2(cx<float> a, cx<float> b, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                         uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qw_v4i, cx2<float>{a, b}), r, voff, soff, 0);
+    // the vector is built from the four values (a bit cast of a cx2 temporary
+    // can be folded into one 16-byte read across two array elements, which
+    // keeps a register array in scratch memory)
+    const qw_v4i d = {__builtin_bit_cast(int, a.re), __builtin_bit_cast(int, a.im), __builtin_bit_cast(int, b.re),
+                      __builtin_bit_cast(int, b.im)};
+    __builtin_amdgcn_raw_buffer_store_b128(d, r, voff, soff, 0);
 }
 __device__ __forceinline__ void bstore2(cx<double> a, cx<double> b, __amdgpu_buffer_rsrc_t r, uint32_t voff,
                                         uint32_t soff)
@@ -387,7 +402,7 @@ __device__ __forceinline__ cx<T> tw16mul(cx<T> a)
         const T c = f32 ? (T)tw16f::c[j] : (T)tw16::c[j];
         const T sj = f32 ? (T)tw16f::s[j] : (T)tw16::s[j];
         const T s = INV ? sj : -sj;
-        return cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+        return cx<T>{fmx(a.re, c, -(a.im * s)), fmx(a.re, s, a.im * c)};
     }
 }
 
@@ -576,12 +591,12 @@ __device__ __forceinline__ void fft_exchange(cx<T> (&vc)[E], int t, cx<T>* lds)
     __syncthreads();
 }
 
-// Runs the passes.  The twiddles of pass p+1 are loaded before pass p's LDS
-// exchange (QW_TW_PREFETCH), so their latency hides behind it.
+// Runs the passes.  With PF the twiddles of pass p+1 are loaded before pass
+// p's LDS exchange, so their latency hides behind it.
 #ifndef QW_TW_PREFETCH
 #define QW_TW_PREFETCH 1
 #endif
-template <typename T, int N, int E, int NC, bool INV, int NS, int R, int... Rest>
+template <typename T, int N, int E, int NC, bool INV, bool PF, int NS, int R, int... Rest>
 __device__ __forceinline__ void fft_run(cx<T> (&v)[NC][E], const cx<T> (&w)[E / R][R], int t,
                                         const cx<T>* __restrict__ tw, cx<T>* lds)
 {
@@ -590,20 +605,22 @@ __device__ __forceinline__ void fft_run(cx<T> (&v)[NC][E], const cx<T> (&w)[E / 
         constexpr int R2 = first_of<Rest...>::value;
         const cx<T>* tw2 = tw + (NS > 1 ? NS * R : 0);
         cx<T> w2[E / R2][R2];
-        if constexpr (QW_TW_PREFETCH) load_twiddles<T, N, E, INV, NS * R, R2>(w2, t, tw2);
+        if constexpr (PF) load_twiddles<T, N, E, INV, NS * R, R2>(w2, t, tw2);
 #pragma unroll
         for (int c = 0; c < NC; ++c) fft_exchange<T, N, E, NS, R>(v[c], t, lds);
-        if constexpr (!QW_TW_PREFETCH) load_twiddles<T, N, E, INV, NS * R, R2>(w2, t, tw2);
-        fft_run<T, N, E, NC, INV, NS * R, Rest...>(v, w2, t, tw2, lds);
+        if constexpr (!PF) load_twiddles<T, N, E, INV, NS * R, R2>(w2, t, tw2);
+        fft_run<T, N, E, NC, INV, PF, NS * R, Rest...>(v, w2, t, tw2, lds);
     }
 }
 
-template <typename T, int N, int E, int NC, bool INV, int R0, int... R>
+// PF: prefetch each pass's twiddles before the previous exchange (hides
+// their latency; holds them in registers across the exchange)
+template <typename T, int N, int E, int NC, bool INV, bool PF = QW_TW_PREFETCH, int R0, int... R>
 __device__ __forceinline__ void fft(sched<R0, R...>, cx<T> (&v)[NC][E], int t, const cx<T>* __restrict__ tw,
                                     cx<T>* lds)
 {
     cx<T> w0[E / R0][R0];  // the first pass (stride 1) has no twiddles
-    fft_run<T, N, E, NC, INV, 1, R0, R...>(v, w0, t, tw, lds);
+    fft_run<T, N, E, NC, INV, PF, 1, R0, R...>(v, w0, t, tw, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -619,10 +636,20 @@ __device__ __forceinline__ void fft(sched<R0, R...>, cx<T> (&v)[NC][E], int t, c
 template <typename T>
 __device__ __forceinline__ void block_prop(cx<T>& top, cx<T>& bot, T C, T a, T bx, T by)
 {
-    const cx<T> t = {C * top.re + a * top.im - by * bot.re + bx * bot.im,
-                     C * top.im - a * top.re - by * bot.im - bx * bot.re};
-    const cx<T> b = {by * top.re + bx * top.im + C * bot.re - a * bot.im,
-                     by * top.im - bx * top.re + C * bot.im + a * bot.re};
+    const cx<T> t = {fmx(bx, bot.im, fmx(-by, bot.re, fmx(a, top.im, C * top.re))),
+                     fmx(-bx, bot.re, fmx(-by, bot.im, fmx(-a, top.re, C * top.im)))};
+    const cx<T> b = {fmx(-a, bot.im, fmx(C, bot.re, fmx(bx, top.im, by * top.re))),
+                     fmx(a, bot.re, fmx(C, bot.im, fmx(-bx, top.re, by * top.im)))};
+    top = t;
+    bot = b;
+}
+
+// the same with a = 0 (the interaction propagator)
+template <typename T>
+__device__ __forceinline__ void block_prop0(cx<T>& top, cx<T>& bot, T C, T bx, T by)
+{
+    const cx<T> t = {fmx(bx, bot.im, fmx(-by, bot.re, C * top.re)), fmx(-bx, bot.re, fmx(-by, bot.im, C * top.im))};
+    const cx<T> b = {fmx(C, bot.re, fmx(bx, top.im, by * top.re)), fmx(C, bot.im, fmx(-bx, top.re, by * top.im))};
     top = t;
     bot = b;
 }

@@ -21,8 +21,10 @@
 // Tuning constants (measured best on MI355X at 2048^2):
 //  - per-lane-group LDS buffer padding in elements (row / column passes);
 //  - columns per workgroup once a column needs >= 128 lanes;
-//  - minimum waves per SIMD the register allocation must allow: 2 for the
-//    row passes, 4 for the column passes with two columns per workgroup.
+//  - minimum waves per SIMD the register allocation must allow: 3 for the
+//    float passes (at most 168 VGPRs: three 256-lane workgroups per CU),
+//    2 for the double row passes (two 512-lane workgroups never fit a CU),
+//    4 for the double column passes.
 #ifndef QW_LDS_EXTRA_ROW
 #define QW_LDS_EXTRA_ROW 8
 #endif
@@ -30,13 +32,24 @@
 #define QW_LDS_EXTRA_COL 4
 #endif
 #ifndef QW_TX_COL
-#define QW_TX_COL 2
+#define QW_TX_COL 1
 #endif
 #ifndef QW_WPE_ROW
-#define QW_WPE_ROW 2
+#define QW_WPE_ROW 3
+#endif
+#ifndef QW_WPE_ROW_F64
+#define QW_WPE_ROW_F64 2
 #endif
 #ifndef QW_WPE_COL
-#define QW_WPE_COL 4
+#define QW_WPE_COL 3
+#endif
+#ifndef QW_WPE_COL_F64
+#define QW_WPE_COL_F64 4
+#endif
+// twiddle prefetch in the column passes (it fits the float column pass's
+// 168 VGPRs without spilling)
+#ifndef QW_TW_PREFETCH_COL
+#define QW_TW_PREFETCH_COL 1
 #endif
 
 namespace qw {
@@ -131,7 +144,7 @@ __device__ __forceinline__ double field_time_factor(int mode, double t, double o
 template <int SERIES, typename T>
 __device__ __forceinline__ void interaction_coeffs(T ax, T ay, T ctau, T& C, T& S)
 {
-    const T a2 = ax * ax + ay * ay;
+    const T a2 = fmx(ax, ax, ay * ay);
     if constexpr (SERIES == 2) {
         T sc;
         cos_sinc_short(ctau * ctau * a2, C, sc);
@@ -161,7 +174,7 @@ __device__ __forceinline__ void apply_interaction(cx<T> (&v)[2][E], const cx<T>*
         const T ax = ax_row * xb.im, ay = ay_row * xb.re;
         T C, Sn;
         interaction_coeffs<SERIES>(ax, ay, ctau, C, Sn);
-        block_prop(v[0][m], v[1][m], C, (T)0, Sn * ax, Sn * ay);
+        block_prop0(v[0][m], v[1][m], C, Sn * ax, Sn * ay);
     }
 }
 
@@ -202,44 +215,105 @@ __device__ __forceinline__ void apply_full_beam(cx<T> (&v)[2][E], const RowArgs&
         const T ax = b.longitudinal ? (T)(-4.0 * b.a0 * b.eps * env * (yl / sqrt(w2)) * s1) : (T)0;
         T C, Sn;
         interaction_coeffs<0>(ax, ay, ctau, C, Sn);
-        block_prop(v[0][m], v[1][m], C, (T)0, Sn * ax, Sn * ay);
+        block_prop0(v[0][m], v[1][m], C, Sn * ax, Sn * ay);
     }
 }
 
 __device__ __forceinline__ int signed_idx(int k, int n) { return k < n / 2 ? k : k - n; }
 
 // ---------------------------------------------------------------------------
+// State layouts.  LAY_ABI is the boundary's psi[ny][nx][4].  LAY_SPLIT is the
+// layout a propagation keeps between its first and last row pass: the two
+// Dirac blocks in separate planes (block A = (psi1, psi4) first, block B =
+// (psi3, psi2) second, each a "block cell" of two complex values), and each
+// 128-byte line of a plane holding an LX x LY patch of block cells:
+//   byte(b, y, x) = b nx ny BC + ((y / LY) (nx / LX) + x / LX) 128 + ((y % LY) LX + x % LX) BC.
+// LX = 2 in both precisions, so a column workgroup of two columns of one
+// block moves whole lines (float: 2 x 4 patches; double: 2 x 2).  A row
+// workgroup of two rows of one block moves whole lines in double and half
+// lines in float, whose other halves the partner tile (the next two rows)
+// moves on the same XCD at the same time (row_pass).  No lane swaps the
+// halves of a cell.
+// ---------------------------------------------------------------------------
+enum { LAY_ABI = 0, LAY_SPLIT = 1 };
+
+template <typename T>
+struct split_geom {
+    static constexpr int BC = 2 * (int)sizeof(cx<T>);  // bytes per block cell
+    static constexpr int LY = sizeof(T) == sizeof(float) ? 4 : 2;  // block cells along y per line
+    static constexpr int LX = 128 / (BC * LY);                     // block cells along x per line
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t split_off(int b, int y, int x, int nx, int ny)
+{
+    using G = split_geom<T>;
+    return (uint32_t)b * (uint32_t)nx * (uint32_t)ny * G::BC +
+           ((uint32_t)(y / G::LY) * (uint32_t)(nx / G::LX) + (uint32_t)(x / G::LX)) * 128u +
+           (uint32_t)(((y % G::LY) * G::LX + (x % G::LX)) * G::BC);
+}
+
+// ---------------------------------------------------------------------------
 // row pass
 // ---------------------------------------------------------------------------
 // One tile of RPW rows of length N (transform with E elements per lane and
 // the radix schedule SCH, LDS stride LL per lane group), threads
-// 0 .. RPW 2 N/E - 1.  lds holds RPW 2 LL elements.
-template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE, int BEAM = 0>
+// 0 .. RPW 2 N/E - 1.  lds holds RPW 2 LL elements.  IN and OUT are the
+// layouts read and written.  With both LAY_SPLIT the tile is 2 RPW rows of
+// one block (lane 2q + r: row parity r); otherwise RPW rows of both blocks
+// (lane 2q + b: block b).  Either way lane 2q + j uses LDS group 2 s + j.
+template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE, int BEAM = 0, int IN = LAY_ABI,
+          int OUT = LAY_ABI>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds, int tid)
 {
     constexpr int NT = N / E, L = 2 * NT;
-    const int blk = tid & 1;  // 0: (psi1, psi4), 1: (psi2, psi3)
+    constexpr bool SPLIT_MAP = IN == LAY_SPLIT && OUT == LAY_SPLIT;
+    using G = split_geom<T>;
+    const int lo = tid & 1;
     const int q = tid >> 1;
     const int s = q / NT;
     const int t = q - s * NT;
-    const int y = tile * RPW + s;
+    int blk, y;
+    if constexpr (SPLIT_MAP) {
+        const int tpb = (a.ny + 2 * RPW - 1) / (2 * RPW);  // tiles per block
+        blk = tile >= tpb ? 1 : 0;
+        y = (tile - blk * tpb) * 2 * RPW + 2 * s + lo;
+    } else {
+        blk = lo;  // 0: (psi1, psi4), 1: (psi3, psi2)
+        y = tile * RPW + s;
+    }
     const bool live = y < a.ny;
-    cx<T>* lb = lds + (2 * s + blk) * LL;
+    cx<T>* lb = lds + (2 * s + lo) * LL;
     const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twx);
     // byte offsets: lane (y, t, block) plus m NT cells per element; a
     // non-live row is pointed past the array (reads zero, writes dropped)
     constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
     const uint32_t bytes = (uint32_t)a.ny * N * CB;
     const uint32_t lane = live ? ((uint32_t)y * N + t) * CB + blk * (CB / 2) : bytes;
+    // split layout: element m at x = t + NT m; linear in m when NT is a whole number of lines
+    constexpr bool SPLIT_LINEAR = NT % G::LX == 0;
+    const uint32_t slane = live ? split_off<T>(blk, y, t, N, a.ny) : bytes;
+    constexpr uint32_t SSTEP = (uint32_t)(NT / G::LX) * 128u;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.src, bytes);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(a.dst, bytes);
 
     cx<T> v[2][E];
+    if constexpr (IN == LAY_ABI) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        cx<T> f;
-        bload2((cx<T>*)nullptr, rs, lane, m * NT * CB, v[0][m], f);
-        v[1][m] = swap_lane_pair(f);
+        for (int m = 0; m < E; ++m) {
+            cx<T> f;
+            bload2((cx<T>*)nullptr, rs, lane, m * NT * CB, v[0][m], f);
+            v[1][m] = swap_lane_pair(f);
+        }
+    } else if constexpr (SPLIT_LINEAR) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) bload2((cx<T>*)nullptr, rs, slane, m * SSTEP, v[0][m], v[1][m]);
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t o = live ? split_off<T>(blk, y, t + NT * m, N, a.ny) : bytes;
+            bload2((cx<T>*)nullptr, rs, o, 0, v[0][m], v[1][m]);
+        }
     }
 
     if constexpr (MODE == ROW_FWD_NORM) {
@@ -296,12 +370,24 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds,
     if constexpr (MODE == ROW_FIRST || MODE == ROW_MID || MODE == ROW_FWD_NORM)
         fft<T, N, E, 2, false>(SCH{}, v, t, tw, lb);
 
+    if constexpr (OUT == LAY_ABI) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rd, lane, m * NT * CB);
+        for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rd, lane, m * NT * CB);
+    } else if constexpr (SPLIT_LINEAR) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) bstore2(v[0][m], v[1][m], rd, slane, m * SSTEP);
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t o = live ? split_off<T>(blk, y, t + NT * m, N, a.ny) : bytes;
+            bstore2(v[0][m], v[1][m], rd, o, 0);
+        }
+    }
 }
 
 template <typename T, int N, int MODE, int BEAM = 0>
-__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_ROW))) void row_pass(RowArgs a)
+__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((
+    amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? QW_WPE_ROW : QW_WPE_ROW_F64))) void row_pass(RowArgs a)
 {
     using S = shape<T, N>;
     __shared__ cx<T> lds[S::RPW * 2 * S::LLR];
@@ -310,59 +396,43 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
         a.dt = a.clock->dt;
         a.k += a.clock->k_base;
     }
-    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM>(a, blockIdx.x, lds, threadIdx.x);
+    // a propagation keeps the split layout from its first row pass to its last
+    constexpr int IN = (MODE == ROW_MID || MODE == ROW_LAST) ? LAY_SPLIT : LAY_ABI;
+    constexpr int OUT = (MODE == ROW_FIRST || MODE == ROW_MID) ? LAY_SPLIT : LAY_ABI;
+    // Middle passes in float: tiles 2P and 2P + 1 (two rows each) share
+    // every line of the split layout.  Workgroups are dealt round-robin to
+    // the 8 XCDs, so the pair goes to the two workgroups an XCD receives one
+    // after the other (blockIdx b and b + 8): they run together, and the
+    // second reader of each line finds it in that XCD's L2.
+    int tile = blockIdx.x;
+    if constexpr (IN == LAY_SPLIT && OUT == LAY_SPLIT && split_geom<T>::LY > 2) {
+        if ((gridDim.x & 15) == 0) {
+            const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
+            tile = 2 * ((i >> 1) * 8 + x) + (i & 1);
+        }
+    }
+    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM, IN, OUT>(a, tile, lds, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // column pass
 // ---------------------------------------------------------------------------
-// One tile of TX columns of length N, threads 0 .. TX 2 N/E - 1; lds holds
-// TX 2 LL elements.
-template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE, int FRAME = 0>
-__device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds, int tid)
+// The kinetic step of a column at signed x index kxs, element m at
+// y = t + NT m, in the order (top, bot) of block blk, 1/(nx ny) included.
+template <typename T, int N, int E, int FRAME>
+__device__ __forceinline__ void apply_kinetic(cx<T> (&v)[2][E], const ColArgs& a, int blk, int kxs, int t)
 {
-    constexpr int NT = N / E, L = 2 * NT;
-    // lane order: block fastest, then the column within the tile, then t, so
-    // a wave reads TX whole cells of each of several rows
-    const int blk = tid & 1;
-    const int cl = (tid >> 1) % TX;
-    const int t = (tid >> 1) / TX;
-    const int x = tile * TX + cl;
-    const bool live = x < a.nx;
-    cx<T>* lb = lds + (2 * cl + blk) * LL;
-    const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twy);
-    constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
-    const uint32_t bytes = (uint32_t)a.nx * N * CB;
-    const uint32_t lane = live ? ((uint32_t)t * a.nx + x) * CB + blk * (CB / 2) : bytes;
-    const uint32_t mstride = (uint32_t)NT * a.nx * CB;  // bytes between a lane's elements
-    const __amdgpu_buffer_rsrc_t rp = make_rsrc(a.psi, bytes);
-
-    cx<T> v[2][E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        cx<T> f;
-        bload2((cx<T>*)nullptr, rp, lane, m * mstride, v[0][m], f);
-        v[1][m] = swap_lane_pair(f);
-    }
-
-    if constexpr (MODE == COL_INV) {
-        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
-    } else {
-        fft<T, N, E, 2, false>(SCH{}, v, t, tw, lb);
-    }
-
+    constexpr int NT = N / E;
     const double c = a.c;
-    const int kxs = signed_idx(live ? x : 0, a.nx);
     const double px = a.dkx * (double)kxs;
-
-    if constexpr (MODE == COL_PROP && FRAME == 1) {
+    const T sgn = blk ? (T)-1 : (T)1;  // sign of the sigma_z term in each lane's order
+    const T ka = sgn * (T)(c * c);
+    const T kx = (T)(c * px);
+    if constexpr (FRAME == 1) {
         // in a frame: K(p + a_m e_y, dt) exp(i vy p_y dt) / (nx ny), from the frame
         // table at (|kx|, ky): ((cos(E dt), sin(E dt)/E)/(nx ny), (cos, sin)(vy p_y dt)),
         // E of the kinetic momentum (px, py + a_m)
         const cx2<T>* kt = reinterpret_cast<const cx2<T>*>(a.ktab) + (size_t)(kxs < 0 ? -kxs : kxs) * N;
-        const T sgn = blk ? (T)-1 : (T)1;
-        const T ka = sgn * (T)(c * c);
-        const T kx = (T)(c * px);
         asm volatile("" ::: "memory");
         int tt = t;
         asm volatile("" : "+v"(tt));
@@ -375,16 +445,12 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
             v[0][m] = mul(v[0][m], q.b);
             v[1][m] = mul(v[1][m], q.b);
         }
-        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
-    } else if constexpr (MODE == COL_PROP) {
+    } else {
         // kinetic propagator K(p, dt) = cos(E dt) - i sin(E dt) H0(p)/E, times 1/(nx ny):
         // the table holds (cos(E dt), sin(E dt)/E)/(nx ny) at (|kx|, |ky|) (E depends on
         // |p| only); the matrix entries are (a, bx, by) = sin(E dt)/E (c^2, c px, c py)
         const int ny2 = N / 2 + 1;
         const cx<T>* kt = reinterpret_cast<const cx<T>*>(a.ktab) + (size_t)(kxs < 0 ? -kxs : kxs) * ny2;
-        const T sgn = blk ? (T)-1 : (T)1;  // sign of the sigma_z term in each lane's order
-        const T ka = sgn * (T)(c * c);
-        const T kx = (T)(c * px);
         const T ky = (T)(c * a.dky);
         asm volatile("" ::: "memory");
         int tt = t;
@@ -395,12 +461,95 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
             const cx<T> cq = kt[kys < 0 ? -kys : kys];
             block_prop(v[0][m], v[1][m], cq.re, cq.im * ka, cq.im * kx, cq.im * ky * (T)kys);
         }
-        fft<T, N, E, 2, true>(SCH{}, v, t, tw, lb);
+    }
+}
+
+// One tile of TX columns of length N, threads 0 .. TX 2 N/E - 1; lds holds
+// TX 2 LL elements.
+template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE, int FRAME = 0, int LAY = LAY_ABI>
+__device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds, int tid)
+{
+    constexpr int NT = N / E, L = 2 * NT;
+    using G = split_geom<T>;
+    // LAY_ABI: lane order block fastest, then the column within the tile, then
+    // t, so a wave reads TX whole cells of each of several rows.  LAY_SPLIT: a
+    // tile is CT = 2 TX columns of one block, lane order column then t.  Lane
+    // j (mod CT) uses LDS group j either way.
+    constexpr int CT = 2 * TX;
+    const int grp = tid & (CT - 1);
+    const int t = tid / CT;
+    int blk, x;
+    if constexpr (LAY == LAY_SPLIT) {
+        const int tpb = (a.nx + CT - 1) / CT;  // tiles per block
+        blk = tile >= tpb ? 1 : 0;
+        x = (tile - blk * tpb) * CT + grp;
+    } else {
+        blk = tid & 1;
+        x = tile * TX + (grp >> 1);
+    }
+    const bool live = x < a.nx;
+    cx<T>* lb = lds + grp * LL;
+    const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.twy);
+    constexpr uint32_t CB = 4 * sizeof(cx<T>);  // bytes per cell
+    const uint32_t bytes = (uint32_t)a.nx * N * CB;
+    const uint32_t lane = live ? ((uint32_t)t * a.nx + x) * CB + blk * (CB / 2) : bytes;
+    const uint32_t mstride = (uint32_t)NT * a.nx * CB;  // bytes between a lane's elements
+    // split layout: element m at y = t + NT m; linear in m when NT is a whole number of lines
+    constexpr bool SPLIT_LINEAR = NT % G::LY == 0;
+    const uint32_t slane = live ? split_off<T>(blk, t, x, a.nx, N) : bytes;
+    // wave-uniform (a scalar offset of the buffer instructions)
+    const uint32_t sstep =
+        __builtin_amdgcn_readfirstlane((uint32_t)(NT / G::LY) * (uint32_t)(a.nx / G::LX) * 128u);
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(a.psi, bytes);
+
+    cx<T> v[2][E];
+    if constexpr (LAY == LAY_ABI) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            cx<T> f;
+            bload2((cx<T>*)nullptr, rp, lane, m * mstride, v[0][m], f);
+            v[1][m] = swap_lane_pair(f);
+        }
+    } else if constexpr (SPLIT_LINEAR) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) bload2((cx<T>*)nullptr, rp, slane, m * sstep, v[0][m], v[1][m]);
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const uint32_t o = live ? split_off<T>(blk, t + NT * m, x, a.nx, N) : bytes;
+            bload2((cx<T>*)nullptr, rp, o, 0, v[0][m], v[1][m]);
+        }
     }
 
-    if constexpr (MODE == COL_PROP || MODE == COL_INV) {
+    if constexpr (MODE == COL_INV) {
+        fft<T, N, E, 2, true, QW_TW_PREFETCH_COL>(SCH{}, v, t, tw, lb);
+    } else {
+        fft<T, N, E, 2, false, QW_TW_PREFETCH_COL>(SCH{}, v, t, tw, lb);
+    }
+
+    const double c = a.c;
+    const int kxs = signed_idx(live ? x : 0, a.nx);
+    const double px = a.dkx * (double)kxs;
+
+    if constexpr (MODE == COL_PROP) {
+        apply_kinetic<T, N, E, FRAME>(v, a, blk, kxs, t);
+        fft<T, N, E, 2, true, QW_TW_PREFETCH_COL>(SCH{}, v, t, tw, lb);
+    }
+
+    if constexpr ((MODE == COL_PROP || MODE == COL_INV) && LAY == LAY_ABI) {
 #pragma unroll
         for (int m = 0; m < E; ++m) bstore2(v[0][m], swap_lane_pair(v[1][m]), rp, lane, m * mstride);
+    } else if constexpr (MODE == COL_PROP || MODE == COL_INV) {
+        if constexpr (SPLIT_LINEAR) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) bstore2(v[0][m], v[1][m], rp, slane, m * sstep);
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const uint32_t o = live ? split_off<T>(blk, t + NT * m, x, a.nx, N) : bytes;
+                bstore2(v[0][m], v[1][m], rp, o, 0);
+            }
+        }
     }
 
     if constexpr (MODE == COL_OBS || MODE == COL_MAPS) {
@@ -492,7 +641,8 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
 }
 
 template <typename T, int N, int MODE, int FRAME = 0>
-__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((amdgpu_waves_per_eu(QW_WPE_COL))) void col_pass(ColArgs a)
+__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
+    amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? QW_WPE_COL : QW_WPE_COL_F64))) void col_pass(ColArgs a)
 {
     using S = shape<T, N>;
     __shared__ cx<T> lds[S::TX * 2 * S::LLC];
@@ -500,7 +650,9 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     // give each XCD a contiguous run of tiles -- neighbouring tiles share
     // cache lines and then meet in the same L2
     const int tile = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
-    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE, FRAME>(a, tile, lds, threadIdx.x);
+    // the propagation's column passes run on the split layout (see row_pass)
+    constexpr int LAY = MODE == COL_PROP ? LAY_SPLIT : LAY_ABI;
+    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE, FRAME, LAY>(a, tile, lds, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -691,7 +843,9 @@ template <typename T, int N>
 hipError_t row_launch_n(int mode, const RowArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
-    const dim3 grid((a.ny + S::RPW - 1) / S::RPW), block(S::RPW * S::L);
+    // ROW_MID tiles are 2 RPW rows of one block: as many workgroups as RPW rows of both
+    const dim3 grid(mode == ROW_MID ? 2 * ((a.ny + 2 * S::RPW - 1) / (2 * S::RPW)) : (a.ny + S::RPW - 1) / S::RPW),
+        block(S::RPW * S::L);
     if (a.beam_mode == QW_BEAM_GAUSSIAN_FULL_) {
         switch (mode) {
         case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST, 1>), grid, block, 0, st, a); break;
@@ -718,7 +872,9 @@ template <typename T, int N>
 hipError_t col_launch_n(int mode, const ColArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
-    const dim3 grid((a.nx + S::TX - 1) / S::TX), block(S::TX * S::L);
+    // COL_PROP tiles are 2 TX columns of one block
+    const dim3 grid(mode == COL_PROP ? 2 * ((a.nx + 2 * S::TX - 1) / (2 * S::TX)) : (a.nx + S::TX - 1) / S::TX),
+        block(S::TX * S::L);
     switch (mode) {
     case COL_PROP:
         if (a.frame) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 1>), grid, block, 0, st, a);
