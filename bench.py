@@ -78,6 +78,96 @@ def measured_counters(kernel: str):
     return {"bytes": k["read_bytes"] + k["write_bytes"], "valu_insts": k.get("valu_insts")}
 
 
+# the symbols the traffic record keys: the whole-state launches of the middle
+# passes (timed per launch for the roofline) and the per-block launches of the
+# two-chain step loop
+COUNTER_KERNELS = {
+    "col_pass": "void qw::col_pass<float, 2048, 0, 0, false>(qw::ColArgs)",
+    "row_pass": "void qw::row_pass<float, 2048, 1, 0, false>(qw::RowArgs)",
+    "col_pass_one_block": "void qw::col_pass<float, 2048, 0, 0, true>(qw::ColArgs)",
+    "row_pass_one_block": "void qw::row_pass<float, 2048, 1, 0, true>(qw::RowArgs)",
+}
+SQ_KEYS = {"SQ_WAVES": "waves", "SQ_INSTS_VALU": "valu_insts", "SQ_INSTS_LDS": "lds_insts",
+           "SQ_LDS_BANK_CONFLICT": "lds_bank_conflicts", "SQ_WAIT_INST_LDS": "wait_inst_lds",
+           "SQ_WAVE_CYCLES": "wave_cycles", "SQ_BUSY_CYCLES": "busy_cycles",
+           "SQ_ACTIVE_INST_VALU": "active_inst_valu"}
+
+
+def read_counter_csvs(d):
+    """{kernel name: {counter: mean value per dispatch}} from the
+    *counter_collection.csv files of one rocprofv3 --pmc output folder."""
+    import csv
+    import glob
+    sums, counts = {}, {}
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    for fn in files:
+        with open(fn, newline="") as f:
+            for row in csv.DictReader(f):
+                key = (row["Kernel_Name"], row["Counter_Name"])
+                sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+                counts.setdefault(key, set()).add((fn, row.get("Dispatch_Id") or row.get("Correlation_Id")))
+    out = {}
+    for (k, c), v in sums.items():
+        out.setdefault(k, {})[c] = v / len(counts[(k, c)])
+    return out
+
+
+def record_counters(d):
+    """Write the traffic record from rocprofv3 --pmc runs kept under d:
+    d/fetch (FETCH_SIZE), d/write (WRITE_SIZE) and d/sq (SQ_ counters) of the
+    counter command, d/copy_fetch and d/copy_write of --copy-probe.  The KiB
+    counters are scaled by the factors that make the copy kernel's read and
+    written KiB equal the bytes it moves.  Prints a summary table."""
+    fetch, write = read_counter_csvs(os.path.join(d, "fetch")), read_counter_csvs(os.path.join(d, "write"))
+    sq = read_counter_csvs(os.path.join(d, "sq")) if os.path.isdir(os.path.join(d, "sq")) else {}
+    cf, cw = read_counter_csvs(os.path.join(d, "copy_fetch")), read_counter_csvs(os.path.join(d, "copy_write"))
+    copy_kib = 2048 * 2048 * 4 * 8 / 1024  # one 2048^2 FP32 state, read once and written once
+    ck = [k for k in cf if "copyBuffer" in k]  # the device-to-device copy (not the fill before it)
+    if not ck:
+        raise SystemExit("no copy kernel in the copy-probe runs")
+    read_scale = copy_kib / cf[ck[0]]["FETCH_SIZE"]
+    write_scale = copy_kib / cw[ck[0]]["WRITE_SIZE"]
+    rec = {"source_sha256": kernel_source_hash(), "read_scale": read_scale, "write_scale": write_scale,
+           "copy_kernel": ck[0],
+           "note": "KiB counters scaled by the copy kernel's factors; bytes per launch; SQ_ counters per launch",
+           "kernels": {}}
+    alg = BYTES_PER_CELL_PASS["f32"] * 2048 * 2048
+    print(f"copy kernel {ck[0]}: FETCH_SIZE {cf[ck[0]]['FETCH_SIZE']:.1f} KiB -> read scale {read_scale:.4f}; "
+          f"WRITE_SIZE {cw[ck[0]]['WRITE_SIZE']:.1f} KiB -> write scale {write_scale:.4f}")
+    print(f"{'kernel':58s} {'FETCH KiB':>10s} {'WRITE KiB':>10s} {'read MiB':>9s} {'write MiB':>9s} "
+          f"{'total/alg':>9s}")
+    for key, name in COUNTER_KERNELS.items():
+        if name not in fetch or name not in write:
+            continue
+        one = key.endswith("one_block")
+        rb = fetch[name]["FETCH_SIZE"] * 1024 * read_scale
+        wb = write[name]["WRITE_SIZE"] * 1024 * write_scale
+        k = {"read_bytes": rb, "write_bytes": wb}
+        for c, short in SQ_KEYS.items():
+            if c in sq.get(name, {}):
+                k[short] = sq[name][c]
+        rec["kernels"][key] = k
+        a = alg / 2 if one else alg
+        print(f"{name:58s} {fetch[name]['FETCH_SIZE']:10.1f} {write[name]['WRITE_SIZE']:10.1f} "
+              f"{rb / 2**20:9.1f} {wb / 2**20:9.1f} {(rb + wb) / a:9.3f}")
+    if sq:
+        print()
+        print(f"{'kernel':58s} {'waves':>8s} {'VALU':>11s} {'VALU/wave':>9s} {'LDS':>9s} {'LDSconfl':>9s} "
+              f"{'WAIT_LDS':>10s}")
+        for key, name in COUNTER_KERNELS.items():
+            q = sq.get(name)
+            if not q or "SQ_WAVES" not in q:
+                continue
+            print(f"{name:58s} {q['SQ_WAVES']:8.0f} {q.get('SQ_INSTS_VALU', 0):11.0f} "
+                  f"{q.get('SQ_INSTS_VALU', 0) / q['SQ_WAVES']:9.1f} {q.get('SQ_INSTS_LDS', 0):9.0f} "
+                  f"{q.get('SQ_LDS_BANK_CONFLICT', 0):9.0f} {q.get('SQ_WAIT_INST_LDS', 0):10.0f}")
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(f"wrote {TRAFFIC_FILE}")
+
+
 def copy_rate(torch, wl, n=50):
     """torch's plain device copy of one 2048^2 FP32 state (128 MiB read and
     128 MiB written): average microseconds, GB/s and bytes moved per copy."""
@@ -368,10 +458,16 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the surrogate network timing")
     ap.add_argument("--no-unfused", action="store_true",
                     help="skip the torch.fft (rocFFT) comparison of the same step")
+    ap.add_argument("--record-counters", metavar="DIR",
+                    help="write the traffic record from rocprofv3 --pmc runs under DIR (fetch/, write/, sq/, "
+                         "copy_fetch/, copy_write/) and exit; runs without a GPU")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
                          "128 MiB written), the reference for bandwidth and traffic counters")
     a = ap.parse_args()
+    if a.record_counters:
+        record_counters(a.record_counters)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the 2048^2 propagation is "
               "measured on a single GPU, with no sharding across GPUs", file=sys.stderr)
@@ -426,7 +522,14 @@ def main():
                 "traffic_bytes_per_launch": traffic,
                 "bytes_per_launch": BYTES_PER_CELL_PASS["f32"] * cells,
                 "avg_launch_us": {k: round(v["avg_us"], 3) for k, v in per.items()},
+                # the timed region as a whole: the two passes' algorithmic
+                # bytes per step over the measured step time.  There the
+                # middle passes of the two Dirac blocks run as two concurrent
+                # chains of per-block launches, so one kernel's tail overlaps
+                # the other chain's work; the per-launch figures above are of
+                # whole-state launches, one at a time on one stream.
                 "step_GBps": round(2 * BYTES_PER_CELL_PASS["f32"] * cells * a.steps / t32 / 1e9, 1)}
+    roofline["step_frac"] = round(roofline["step_GBps"] / HBM_PEAK_GBS, 4)
     if counters is not None and counters["valu_insts"]:
         # the second limit: wave-level FP32 VALU issue (no packed FP32), one
         # instruction per SIMD every 4 cycles: 256 CUs x 4 SIMDs x 2.4 GHz / 4

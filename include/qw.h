@@ -161,13 +161,20 @@ int qw_init_packet(qw_ctx h, void *psi, const qw_packet *e, void *hip_stream);
  * (n = 0 enqueues nothing).  2n + 1 kernels: one row pass V(t0, dt/2) F_x,
  * then n column passes F_y^-1 K(dt) F_y interleaved with n - 1 row passes
  * F_x V(t_k, dt) F_x^-1, and a last row pass V(t_n, dt/2) F_x^-1.
- * With n > 64, timing off and hip_stream not being captured by the caller,
- * the middle steps run as replays of one
- * HIP graph of 64 (column, row) pass pairs, whose row passes read t_k from
- * a step clock in the workspace; the graph is captured on a stream of the
- * library's own at the first such call and again whenever psi, the beam or
- * the frame differ from that capture's (the graph and the stream live until
- * qw_destroy).  The results equal those of direct launches bit for bit. */
+ * With timing off and hip_stream not being captured by the caller, the
+ * middle passes of the two Dirac blocks (A = (psi1, psi4), B = (psi3, psi2),
+ * which the propagators never couple) run as two chains of per-block
+ * launches, A on hip_stream and B on a stream of the library's own, forked
+ * from hip_stream after the first row pass and joined to it before the
+ * last; for n > 64 they run as replays of one HIP graph of 64 (column, row)
+ * pass pairs per block, whose row passes read t_k from a step clock in the
+ * workspace.  The graph is captured on streams of the library's own at the
+ * first such call and again whenever psi, the beam or the frame differ from
+ * that capture's (graph, streams and events live until qw_destroy).  With
+ * timing on, or under the caller's capture, every pass covers both blocks on
+ * hip_stream.  The results are the same bit for bit either way.
+ * In FP32 the kinetic table carries, besides 1/(nx ny), the factor that
+ * undoes the transforms' mean loss of norm (qw_transform_gain). */
 int qw_step_n(qw_ctx h, void *psi, int64_t n, double t0, double dt, void *hip_stream);
 
 /* Observables of psi (not modified) into out_host (host memory), laid out as
@@ -197,6 +204,17 @@ int qw_momentum_maps(qw_ctx h, const void *psi, double *out, int64_t out_len, vo
  * then clears the counters.  Enabling adds event records between launches. */
 int qw_kernel_timing(qw_ctx h, int enable);
 int qw_kernel_times(qw_ctx h, double *out, int32_t out_len, void *hip_stream);
+
+/* Mean squared-norm gain of one transform of length n (a power of two, 8 ..
+ * 4096) in the given precision, as the library models it: in FP32 each
+ * rotation constant and twiddle is the nearest float of its cos and of its
+ * sin (phase within half a unit in the last place), so its squared
+ * magnitude falls a little short of 1; averaged over each pass's inputs the
+ * passes' gains multiply.  The step loop multiplies K(dt) by
+ * 1/(gain(nx) gain(ny)), which keeps the norm of a float step on average.
+ * QW_F64: 1.  Host arithmetic only (no device work); batch_variant < 0
+ * takes the single-instance plan, v >= 0 the batched schedule variant v. */
+int qw_transform_gain(int32_t n, int32_t precision, int32_t batch_variant, double *gain);
 
 /* Message of the last failure on h (or of the last failed qw_init_grid when
  * h is NULL).  Valid until the next call on h. */

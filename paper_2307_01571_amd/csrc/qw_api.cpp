@@ -91,6 +91,11 @@ struct qw_ctx_s {
     // the step loop's captured chunk (it works on the workspace plane): valid
     // for exec_psi and the beam/frame state of args_version
     hipStream_t cap = nullptr;
+    // the middle passes of the two Dirac blocks run as two chains: block A on
+    // the caller's stream (or cap), block B on side (or cap_side), forked from
+    // and joined back into the first by the events
+    hipStream_t side = nullptr, cap_side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr, cap_fork = nullptr, cap_join = nullptr;
     hipGraphExec_t exec = nullptr;
     // recorded on the caller's stream after the replays of each call: the
     // executable graph is destroyed only once its last replay has finished
@@ -194,6 +199,12 @@ int ensure_kinetic_table(qw_ctx h, double dt, hipStream_t s)
     if (h->ktab_valid && h->ktab_dt == dt && h->ktab_frame.vy == h->frame.vy && h->ktab_frame.a_m == h->frame.a_m)
         return QW_OK;
     qw::KineticArgs k = qwh::kinetic_args(h->g, dt);
+    if (f32(h)) {
+        // the float transforms' mean loss of norm, undone in K (see transform_gain_f32)
+        int rx[8], ry[8];
+        const int nrx = qw::plan_radices_f32(h->g.nx, rx, 8), nry = qw::plan_radices_f32(h->g.ny, ry, 8);
+        k.inv_cells *= qwh::kinetic_norm_factor(true, rx, nrx, ry, nry);
+    }
     void* kt = h->ws + h->lay.ktab;
     hipError_t e;
     if (qwh::frame_active(h->frame)) {
@@ -240,6 +251,51 @@ qw::ColArgs col_args(qw_ctx h, void* psi)
 // middle steps per captured chunk of the step loop
 constexpr int kGraphSteps = 64;
 
+// the library's streams and events of the step loop, created once per
+// context with its device current (default priority, non-blocking)
+hipError_t ensure_streams(qw_ctx h)
+{
+    if (h->cap) return hipSuccess;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != h->device) e = hipSetDevice(h->device);
+    for (hipStream_t* st : {&h->cap, &h->side, &h->cap_side})
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&h->exec_done, &h->fork_ev, &h->join_ev, &h->cap_fork, &h->cap_join})
+        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+    if (prev != h->device) (void)hipSetDevice(prev);
+    return e;
+}
+
+// Middle steps j0 .. j0 + count - 1 (column pass, then the row pass V(t_k, dt)
+// with k = the step) and, if final_col, the column pass of the last step,
+// as two chains: block A on a, block B on b, b forked from a before and a
+// joined to b after (the blocks never couple, so the chains are independent
+// and one chain's kernels fill the GPU while the other's start or drain).
+hipError_t enqueue_middle(qw_ctx h, hipStream_t a, hipStream_t b, hipEvent_t fork, hipEvent_t join, qw::RowArgs r,
+                          qw::ColArgs c, int64_t j0, int64_t count, bool final_col)
+{
+    hipError_t e = hipEventRecord(fork, a);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b, fork, 0);
+    r.tau_frac = 1.0;  // V(t_k, dt/2) V(t_k, dt/2) = V(t_k, dt)
+    for (int64_t j = 0; j < count && e == hipSuccess; ++j) {
+        r.k = j0 + j;
+        for (int blk = 1; blk <= 2 && e == hipSuccess; ++blk) {
+            hipStream_t st = blk == 1 ? a : b;
+            c.one_block = r.one_block = blk;
+            e = launch_col(h, qw::COL_PROP, c, st);
+            if (e == hipSuccess) e = launch_row(h, qw::ROW_MID, r, st);
+        }
+    }
+    for (int blk = 1; blk <= 2 && final_col && e == hipSuccess; ++blk) {
+        c.one_block = blk;
+        e = launch_col(h, qw::COL_PROP, c, blk == 1 ? a : b);
+    }
+    if (e == hipSuccess) e = hipEventRecord(join, b);
+    if (e == hipSuccess) e = hipStreamWaitEvent(a, join, 0);
+    return e;
+}
+
 // the step loop's device clock: 4 doubles at the end of the 256-double
 // scalars slot ([0] packet norm, [8, 8 + 3B + 3) observables, B <= 33)
 constexpr int kClockSlot = 248;
@@ -273,29 +329,15 @@ hipError_t ensure_graph(qw_ctx h, void* psi, qw::RowArgs r, const qw::ColArgs& c
 {
     if (h->exec && h->exec_psi == psi && h->exec_version == h->args_version) return hipSuccess;
     drop_graph(h);
-    hipError_t e = hipSuccess;
-    if (!h->cap) {
-        int prev = 0;
-        e = hipGetDevice(&prev);
-        if (e == hipSuccess && prev != h->device) e = hipSetDevice(h->device);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
-        if (e == hipSuccess && !h->exec_done) e = hipEventCreateWithFlags(&h->exec_done, hipEventDisableTiming);
-        if (prev != h->device) (void)hipSetDevice(prev);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = ensure_streams(h);
+    if (e != hipSuccess) return e;
     qw::StepClock* clk = step_clock(h);
     r.clock = clk;
     r.t0 = 0.0;
     r.dt = 0.0;
-    r.tau_frac = 1.0;  // V(t_k, dt/2) V(t_k, dt/2) = V(t_k, dt)
     e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = hipSuccess;
-    for (int j = 0; j < kGraphSteps && le == hipSuccess; ++j) {
-        le = launch_col(h, qw::COL_PROP, c, h->cap);
-        r.k = j;
-        if (le == hipSuccess) le = launch_row(h, qw::ROW_MID, r, h->cap);
-    }
+    hipError_t le = enqueue_middle(h, h->cap, h->cap_side, h->cap_fork, h->cap_join, r, c, 0, kGraphSteps, false);
     if (le == hipSuccess) le = qw::launch_clock_advance(clk, kGraphSteps, h->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(h->cap, &g);
@@ -463,14 +505,19 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
     }
     int64_t k0 = 1;
     // a caller capturing its own stream (or a stream whose state cannot be
-    // queried) gets the plain launches
+    // queried), or per-launch timing, gets plain launches on the caller's
+    // stream; otherwise the two blocks' chains (enqueue_middle), replayed as
+    // a captured chunk for every kGraphSteps steps
     hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
-    bool replay = !h->timing && n - 1 >= kGraphSteps;
-    if (replay && hipStreamIsCapturing(s, &cap_status) != hipSuccess) {
+    bool chains = !h->timing;
+    if (chains && hipStreamIsCapturing(s, &cap_status) != hipSuccess) {
         (void)hipGetLastError();
-        replay = false;
+        chains = false;
     }
-    if (e == hipSuccess && replay && cap_status == hipStreamCaptureStatusNone) {
+    chains = chains && cap_status == hipStreamCaptureStatusNone;
+    if (e == hipSuccess && chains) e = ensure_streams(h);
+    const bool replay = chains && n - 1 >= kGraphSteps;
+    if (e == hipSuccess && replay) {
         // middle steps 1 .. chunks kGraphSteps as replays of one captured chunk
         qw::StepClock* clk = step_clock(h);
         e = qw::launch_clock_set(clk, t0, dt, 1, s);
@@ -479,6 +526,15 @@ int qw_step_n(qw_ctx h, void* psi, int64_t n, double t0, double dt, void* hip_st
         for (int64_t q = 0; q < chunks && e == hipSuccess; ++q) e = hipGraphLaunch(h->exec, s);
         if (e == hipSuccess) e = hipEventRecord(h->exec_done, s);
         k0 += chunks * kGraphSteps;
+    }
+    if (e == hipSuccess && chains) {
+        // the remaining middle steps and the last column pass, then R_last
+        e = enqueue_middle(h, s, h->side, h->fork_ev, h->join_ev, r, c, k0, n - k0, true);
+        r.k = n;
+        r.tau_frac = 0.5;
+        r.dst = psi;
+        if (e == hipSuccess) e = launch_row(h, qw::ROW_LAST, r, s);
+        k0 = n + 1;
     }
     for (int64_t k = k0; k <= n && e == hipSuccess; ++k) {
         e = timed(h, 1, s, [&] { return launch_col(h, qw::COL_PROP, c, s); });
@@ -547,6 +603,25 @@ int qw_momentum_maps(qw_ctx h, const void* psi, double* out, int64_t out_len, vo
     return QW_OK;
 }
 
+int qw_transform_gain(int32_t n, int32_t precision, int32_t batch_variant, double* gain)
+{
+    if (!gain) return fail(nullptr, QW_E_ARG, "gain is NULL");
+    if (precision != QW_F32 && precision != QW_F64) return fail(nullptr, QW_E_ARG, "unknown precision %d", precision);
+    const bool single = batch_variant < 0;
+    const bool sp = precision == QW_F32;
+    int r[16];
+    int cnt = 0;
+    if (n >= 2 && (n & (n - 1)) == 0) {
+        const int lg = qwh::ilog2(n);
+        cnt = single ? (sp ? qw::plan_radices_f32(n, r, 16) : qw::plan_radices_f64(n, r, 16))
+                     : (sp ? qw::batch_variant_f32(lg, batch_variant, r, 16)
+                           : qw::batch_variant_f64(lg, batch_variant, r, 16));
+    }
+    if (cnt <= 0) return fail(nullptr, QW_E_ARG, "no %s transform of length %d", single ? "plan" : "schedule variant", n);
+    *gain = sp ? qwh::transform_gain_f32(r, cnt) : 1.0;
+    return QW_OK;
+}
+
 int qw_kernel_timing(qw_ctx h, int enable)
 {
     if (!h) return fail(nullptr, QW_E_ARG, "context is NULL");
@@ -588,8 +663,11 @@ void qw_destroy(qw_ctx h)
 {
     if (!h) return;
     drop_graph(h);  // waits for the last replay
-    if (h->exec_done) (void)hipEventDestroy(h->exec_done);
-    if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->side) (void)hipStreamSynchronize(h->side);
+    for (hipEvent_t ev : {h->exec_done, h->fork_ev, h->join_ev, h->cap_fork, h->cap_join})
+        if (ev) (void)hipEventDestroy(ev);
+    for (hipStream_t st : {h->cap, h->side, h->cap_side})
+        if (st) (void)hipStreamDestroy(st);
     for (auto& t : h->timed) {
         // timing brackets still pending on a stream: wait for them first
         (void)hipEventSynchronize(t.b);

@@ -300,6 +300,7 @@ void apply_variants(qw_batch b)
         d.tw_col = b->ws + b->lay.tw.at({d.lgy, d.col_var});
     }
     b->desc_dirty = true;
+    b->ktab_valid = false;  // the kinetic tables carry the schedules' norm factors
 }
 
 // copy the host descriptors to the workspace; waits, so the host copy may change afterwards
@@ -390,7 +391,14 @@ int ensure_ktab(qw_batch b, double dt, hipStream_t s)
         g.lx = std::get<2>(key);
         g.ly = std::get<3>(key);
         g.c = std::get<4>(key);
-        const hipError_t e = b->p.kinetic(b->ws + kv.second, qwh::kinetic_args(g, dt), s);
+        qw::KineticArgs k = qwh::kinetic_args(g, dt);
+        // the mean loss of norm of the float transforms of the middle passes'
+        // schedules, undone in K (see transform_gain_f32)
+        const int lgx = ilog2(g.nx), lgy = ilog2(g.ny);
+        int rx[16], ry[16];
+        const int nrx = b->p.variant(lgx, b->row_var[lgx], rx, 16), nry = b->p.variant(lgy, b->col_var[lgy], ry, 16);
+        k.inv_cells *= qwh::kinetic_norm_factor(b->p.f32, rx, nrx, ry, nry);
+        const hipError_t e = b->p.kinetic(b->ws + kv.second, k, s);
         if (e != hipSuccess) return bhip(b, e, "kinetic table kernel");
     }
     b->ktab_valid = true;

@@ -369,25 +369,15 @@ struct tw16 {
                                      -0.38268343236508977173};
 };
 
-// The same rotations as float pairs chosen jointly rather than each rounded
-// to nearest.  Rounded separately, every pair has c^2 + s^2 short of 1 by
-// 3e-8 (j = 2 mod 4) or 6e-8 (odd j), so an FP32 transform would shrink the
-// norm by about 5e-8 every time and a step (four transforms) by 2e-7.  Here
-// odd j take the neighbouring pair 7e-9 above 1; for j = 2 mod 4 no pair
-// within a few units in the last place does better than the nearest one, so
-// j = 2, 10 take the pair 5e-8 above 1 and j = 6, 14 the nearest one, 3.4e-8
-// below: over the radix-16 and radix-8 butterflies the errors then average to
-// about +4e-9.  Every value stays within 1.3 units in the last place of the
-// exact one.
-struct tw16f {
-    static constexpr float A = 0.9238795638084412f;  // cos(pi/8) + 1 ulp
-    static constexpr float B = 0.3826833665370941f;  // sin(pi/8) - 2 ulp
-    static constexpr float P = 0.7071067690849304f;  // sqrt(1/2), nearest
-    static constexpr float Q = 0.7071068286895752f;  // sqrt(1/2) + 1 ulp
-    static constexpr float c[16] = {1.0f, A, Q, B, 0.0f, -B, -P, -A, -1.0f, -A, -Q, -B, 0.0f, B, P, A};
-    static constexpr float s[16] = {0.0f, B, P, A, 1.0f, A, P, B, 0.0f, -B, -P, -A, -1.0f, -A, -P, -B};
-};
-
+// In float the rotations are the nearest float of each of c and s: the
+// phase of every pair is then within half a unit in the last place of the
+// exact one.  Their squared magnitudes fall short of 1 (by 3e-8 for j = 2
+// mod 4, 6e-8 for odd j), a small loss of norm in every transform that is
+// the same from step to step; the step loop takes it out on average through
+// its kinetic table (the host's transform-gain model of the kinetic step).
+// Pairs chosen for c^2 + s^2 closest to 1 instead carry phase errors of up
+// to about 1.3 units in the last place of one sign, which the band
+// probabilities pick up coherently, step after step.
 // multiply by exp(-+2 pi i j / 16) with j a compile-time constant
 template <typename T, bool INV, int J>
 __device__ __forceinline__ cx<T> tw16mul(cx<T> a)
@@ -398,9 +388,8 @@ __device__ __forceinline__ cx<T> tw16mul(cx<T> a)
     else if constexpr (j == 8) return cx<T>{-a.re, -a.im};
     else if constexpr (j == 12) return rot90<T, !INV>(a);
     else {
-        constexpr bool f32 = sizeof(T) == sizeof(float);
-        const T c = f32 ? (T)tw16f::c[j] : (T)tw16::c[j];
-        const T sj = f32 ? (T)tw16f::s[j] : (T)tw16::s[j];
+        const T c = (T)tw16::c[j];
+        const T sj = (T)tw16::s[j];
         const T s = INV ? sj : -sj;
         return cx<T>{fmx(a.re, c, -(a.im * s)), fmx(a.re, s, a.im * c)};
     }

@@ -185,6 +185,60 @@ inline qw::BeamArgs beam_args(const qw_grid& g, const qw_beam& b)
     return a;
 }
 
+// Mean squared-norm gain of one float transform with the given radices.  The
+// per-pass twiddles and the radix-8/16 rotation constants are float pairs
+// (c, s), each rounded to nearest, with c^2 + s^2 a little under 1.  A pass
+// of radix R and stride ns multiplies input r of butterfly j by the twiddle
+// exp(-+2 pi i (j mod ns) r / (ns R)) and then by the butterfly's rotation
+// constants, which for input r are w16^(q s), s = 0..3, with q = r mod 4
+// (R = 16), or w16^(2 q s) with q = r mod 2 (R = 8), each on a quarter of
+// its energy; R = 2, 4 use only +-1 and +-i.  Averaged over the inputs, the
+// passes' gains multiply.  Forward and inverse transforms use conjugate
+// pairs of the same magnitudes.
+inline double transform_gain_f32(const int* radices, int count)
+{
+    auto mag2 = [](double angle) {
+        const double c = (double)(float)std::cos(angle), s = (double)(float)std::sin(angle);
+        return c * c + s * s;
+    };
+    auto w16 = [&](int j) { return (j & 3) == 0 ? 1.0 : mag2(2.0 * kPi * (j & 15) / 16.0); };
+    double gain = 1.0;
+    int ns = 1;
+    for (int p = 0; p < count; ++p) {
+        const int R = radices[p];
+        double sum = 0.0;
+        for (int r = 0; r < R; ++r) {
+            double rot = 1.0;
+            if (R == 8 || R == 16) {
+                const int q = R == 16 ? (r & 3) : (r & 1);
+                rot = 0.0;
+                for (int s = 0; s < 4; ++s) rot += w16((R == 16 ? 1 : 2) * q * s);
+                rot *= 0.25;
+            }
+            double tw = 1.0;
+            if (ns > 1) {
+                tw = 0.0;
+                for (int jm = 0; jm < ns; ++jm) tw += mag2(2.0 * kPi * (double)jm * r / ((double)ns * R));
+                tw /= ns;
+            }
+            sum += tw * rot;
+        }
+        gain *= sum / R;
+        ns *= R;
+    }
+    return gain;
+}
+
+// The factor the kinetic table carries besides 1/(nx ny) so that a float
+// step keeps the norm on average: a step makes two transforms of each
+// length, so its squared-norm gain is (gx gy)^2 and the amplitude factor
+// 1/(gx gy) undoes it.  FP64 rotations are exact to 1e-16: factor 1.
+inline double kinetic_norm_factor(bool f32, const int* rx, int nrx, const int* ry, int nry)
+{
+    if (!f32) return 1.0;
+    return 1.0 / (transform_gain_f32(rx, nrx) * transform_gain_f32(ry, nry));
+}
+
 inline qw::KineticArgs kinetic_args(const qw_grid& g, double dt)
 {
     qw::KineticArgs k{};

@@ -263,7 +263,7 @@ __device__ __forceinline__ uint32_t split_off(int b, int y, int x, int nx, int n
 // one block (lane 2q + r: row parity r); otherwise RPW rows of both blocks
 // (lane 2q + b: block b).  Either way lane 2q + j uses LDS group 2 s + j.
 template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE, int BEAM = 0, int IN = LAY_ABI,
-          int OUT = LAY_ABI>
+          int OUT = LAY_ABI, bool ONE = false>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds, int tid)
 {
     constexpr int NT = N / E, L = 2 * NT;
@@ -276,8 +276,8 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds,
     int blk, y;
     if constexpr (SPLIT_MAP) {
         const int tpb = (a.ny + 2 * RPW - 1) / (2 * RPW);  // tiles per block
-        blk = tile >= tpb ? 1 : 0;
-        y = (tile - blk * tpb) * 2 * RPW + 2 * s + lo;
+        blk = ONE ? a.one_block - 1 : (tile >= tpb ? 1 : 0);
+        y = (ONE ? tile : tile - blk * tpb) * 2 * RPW + 2 * s + lo;
     } else {
         blk = lo;  // 0: (psi1, psi4), 1: (psi3, psi2)
         y = tile * RPW + s;
@@ -385,7 +385,9 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds,
     }
 }
 
-template <typename T, int N, int MODE, int BEAM = 0>
+// ONE: the launch covers the block a.one_block only (a separate symbol, so a
+// kernel trace tells the per-block launches from the whole-state ones)
+template <typename T, int N, int MODE, int BEAM = 0, bool ONE = false>
 __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((
     amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? QW_WPE_ROW : QW_WPE_ROW_F64))) void row_pass(RowArgs a)
 {
@@ -411,7 +413,7 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
             tile = 2 * ((i >> 1) * 8 + x) + (i & 1);
         }
     }
-    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM, IN, OUT>(a, tile, lds, threadIdx.x);
+    row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM, IN, OUT, ONE>(a, tile, lds, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,7 +468,8 @@ __device__ __forceinline__ void apply_kinetic(cx<T> (&v)[2][E], const ColArgs& a
 
 // One tile of TX columns of length N, threads 0 .. TX 2 N/E - 1; lds holds
 // TX 2 LL elements.
-template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE, int FRAME = 0, int LAY = LAY_ABI>
+template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE, int FRAME = 0, int LAY = LAY_ABI,
+          bool ONE = false>
 __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds, int tid)
 {
     constexpr int NT = N / E, L = 2 * NT;
@@ -480,9 +483,22 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
     const int t = tid / CT;
     int blk, x;
     if constexpr (LAY == LAY_SPLIT) {
+        // Tile order: in a launch of both blocks, tiles 2j and 2j + 1 are
+        // column group j of blocks A and B; group j is the (j/2)-th group
+        // from the left for even j, from the right for odd j.  Tiles that
+        // follow each other run on one XCD at nearly the same time, so the
+        // rows of the kinetic table they read (indexed by |kx|, shared by
+        // columns x and nx - x and by both blocks) come from that XCD's L2.
         const int tpb = (a.nx + CT - 1) / CT;  // tiles per block
-        blk = tile >= tpb ? 1 : 0;
-        x = (tile - blk * tpb) * CT + grp;
+        int j;
+        if constexpr (ONE) {
+            blk = a.one_block - 1;
+            j = tile;
+        } else {
+            blk = tile & 1;
+            j = tile >> 1;
+        }
+        x = ((j & 1) ? tpb - 1 - (j >> 1) : (j >> 1)) * CT + grp;
     } else {
         blk = tid & 1;
         x = tile * TX + (grp >> 1);
@@ -640,7 +656,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
     }
 }
 
-template <typename T, int N, int MODE, int FRAME = 0>
+template <typename T, int N, int MODE, int FRAME = 0, bool ONE = false>
 __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? QW_WPE_COL : QW_WPE_COL_F64))) void col_pass(ColArgs a)
 {
@@ -648,11 +664,11 @@ __global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
     __shared__ cx<T> lds[S::TX * 2 * S::LLC];
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
     // give each XCD a contiguous run of tiles -- neighbouring tiles share
-    // cache lines and then meet in the same L2
+    // cache lines (or kinetic table rows) and then meet in the same L2
     const int tile = (gridDim.x & 7) == 0 ? (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3) : blockIdx.x;
     // the propagation's column passes run on the split layout (see row_pass)
     constexpr int LAY = MODE == COL_PROP ? LAY_SPLIT : LAY_ABI;
-    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE, FRAME, LAY>(a, tile, lds, threadIdx.x);
+    col_tile<T, N, S::E, typename plan<T, N>::S, S::TX, S::LLC, MODE, FRAME, LAY, ONE>(a, tile, lds, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,46 +689,13 @@ __device__ void fill_pass_twiddles(cx<double>* tmp, int i, int off)
     if constexpr (sizeof...(Rest) > 0) fill_pass_twiddles<NS * R, Rest...>(tmp, i, off + (NS > 1 ? NS * R : 0));
 }
 
-// (c, s) rounded to float jointly: among the floats within two units in the
-// last place of each, the pair whose c^2 + s^2 is closest to 1 (ties: the
-// one closest to (c, s)).  Rounded separately, a twiddle's squared magnitude
-// is off by up to 1.2e-7, a bias the norm of an FP32 transform would carry.
-__device__ inline cx<float> unit_pair_f32(double c, double s)
-{
-    float cs[5], ss[5];
-    cs[2] = (float)c;
-    ss[2] = (float)s;
-    cs[1] = nextafterf(cs[2], -INFINITY);
-    cs[0] = nextafterf(cs[1], -INFINITY);
-    cs[3] = nextafterf(cs[2], INFINITY);
-    cs[4] = nextafterf(cs[3], INFINITY);
-    ss[1] = nextafterf(ss[2], -INFINITY);
-    ss[0] = nextafterf(ss[1], -INFINITY);
-    ss[3] = nextafterf(ss[2], INFINITY);
-    ss[4] = nextafterf(ss[3], INFINITY);
-    cx<float> best{cs[2], ss[2]};
-    double be = fabs((double)cs[2] * cs[2] + (double)ss[2] * ss[2] - 1.0);
-    double bd = fabs(cs[2] - c) + fabs(ss[2] - s);
-    for (int a = 0; a < 5; ++a)
-        for (int b = 0; b < 5; ++b) {
-            const double e = fabs((double)cs[a] * cs[a] + (double)ss[b] * ss[b] - 1.0);
-            const double d = fabs(cs[a] - c) + fabs(ss[b] - s);
-            if (e < be || (e == be && d < bd)) {
-                best = cx<float>{cs[a], ss[b]};
-                be = e;
-                bd = d;
-            }
-        }
-    return best;
-}
-
 template <typename T, int... R>
 __device__ void pass_twiddle(sched<R...>, cx<T>* tw, int i)
 {
     cx<double> v{1.0, 0.0};
     fill_pass_twiddles<1, R...>(&v, i, 0);
-    if constexpr (sizeof(T) == sizeof(float)) tw[i] = unit_pair_f32(v.re, v.im);
-    else tw[i] = cx<T>{(T)v.re, (T)v.im};
+    // each of c and s rounded to nearest (see the rotation constants)
+    tw[i] = cx<T>{(T)v.re, (T)v.im};
 }
 
 template <typename T, int N, typename SCH = typename plan<T, N>::S>
@@ -843,13 +826,18 @@ template <typename T, int N>
 hipError_t row_launch_n(int mode, const RowArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
-    // ROW_MID tiles are 2 RPW rows of one block: as many workgroups as RPW rows of both
-    const dim3 grid(mode == ROW_MID ? 2 * ((a.ny + 2 * S::RPW - 1) / (2 * S::RPW)) : (a.ny + S::RPW - 1) / S::RPW),
+    // ROW_MID tiles are 2 RPW rows of one block: as many workgroups as RPW
+    // rows of both blocks, or half as many for one block
+    const int nb = a.one_block ? 1 : 2;
+    const dim3 grid(mode == ROW_MID ? nb * ((a.ny + 2 * S::RPW - 1) / (2 * S::RPW)) : (a.ny + S::RPW - 1) / S::RPW),
         block(S::RPW * S::L);
     if (a.beam_mode == QW_BEAM_GAUSSIAN_FULL_) {
         switch (mode) {
         case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST, 1>), grid, block, 0, st, a); break;
-        case ROW_MID: hipLaunchKernelGGL((row_pass<T, N, ROW_MID, 1>), grid, block, 0, st, a); break;
+        case ROW_MID:
+            if (a.one_block) hipLaunchKernelGGL((row_pass<T, N, ROW_MID, 1, true>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((row_pass<T, N, ROW_MID, 1>), grid, block, 0, st, a);
+            break;
         case ROW_LAST: hipLaunchKernelGGL((row_pass<T, N, ROW_LAST, 1>), grid, block, 0, st, a); break;
         case ROW_FWD_NORM: hipLaunchKernelGGL((row_pass<T, N, ROW_FWD_NORM>), grid, block, 0, st, a); break;
         case ROW_INV_SCALE: hipLaunchKernelGGL((row_pass<T, N, ROW_INV_SCALE>), grid, block, 0, st, a); break;
@@ -859,7 +847,10 @@ hipError_t row_launch_n(int mode, const RowArgs& a, hipStream_t st)
     }
     switch (mode) {
     case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST>), grid, block, 0, st, a); break;
-    case ROW_MID: hipLaunchKernelGGL((row_pass<T, N, ROW_MID>), grid, block, 0, st, a); break;
+    case ROW_MID:
+        if (a.one_block) hipLaunchKernelGGL((row_pass<T, N, ROW_MID, 0, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((row_pass<T, N, ROW_MID>), grid, block, 0, st, a);
+        break;
     case ROW_LAST: hipLaunchKernelGGL((row_pass<T, N, ROW_LAST>), grid, block, 0, st, a); break;
     case ROW_FWD_NORM: hipLaunchKernelGGL((row_pass<T, N, ROW_FWD_NORM>), grid, block, 0, st, a); break;
     case ROW_INV_SCALE: hipLaunchKernelGGL((row_pass<T, N, ROW_INV_SCALE>), grid, block, 0, st, a); break;
@@ -872,12 +863,15 @@ template <typename T, int N>
 hipError_t col_launch_n(int mode, const ColArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
-    // COL_PROP tiles are 2 TX columns of one block
-    const dim3 grid(mode == COL_PROP ? 2 * ((a.nx + 2 * S::TX - 1) / (2 * S::TX)) : (a.nx + S::TX - 1) / S::TX),
+    // COL_PROP tiles are 2 TX columns of one block (of both blocks, or of one)
+    const int nb = a.one_block ? 1 : 2;
+    const dim3 grid(mode == COL_PROP ? nb * ((a.nx + 2 * S::TX - 1) / (2 * S::TX)) : (a.nx + S::TX - 1) / S::TX),
         block(S::TX * S::L);
     switch (mode) {
     case COL_PROP:
-        if (a.frame) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 1>), grid, block, 0, st, a);
+        if (a.frame && a.one_block) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 1, true>), grid, block, 0, st, a);
+        else if (a.frame) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 1>), grid, block, 0, st, a);
+        else if (a.one_block) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 0, true>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((col_pass<T, N, COL_PROP>), grid, block, 0, st, a);
         break;
     case COL_INV: hipLaunchKernelGGL((col_pass<T, N, COL_INV>), grid, block, 0, st, a); break;
@@ -919,6 +913,25 @@ hipError_t launch_col(int mode, int ny, const ColArgs& a, hipStream_t st)
     QW_SIZE_SWITCH(ny, QW_CALL)
 #undef QW_CALL
     return hipErrorInvalidValue;
+}
+
+template <int... R>
+int sched_radices(sched<R...>, int* radices, int max_radices)
+{
+    const int r[] = {R...};
+    const int n = (int)(sizeof(r) / sizeof(r[0]));
+    for (int i = 0; i < n && i < max_radices; ++i) radices[i] = r[i];
+    return n;
+}
+
+// the radices of the transform plan of length n (0: no plan)
+template <typename T>
+int plan_radices(int n, int* radices, int max_radices)
+{
+#define QW_CALL(NN) sched_radices(typename plan<T, NN>::S{}, radices, max_radices)
+    QW_SIZE_SWITCH(n, QW_CALL)
+#undef QW_CALL
+    return 0;
 }
 
 template <typename T>
@@ -997,6 +1010,7 @@ hipError_t launch_packet(void* psi, double* rownorm, const PacketArgs& e, hipStr
         return launch_col<T>(mode, ny, a, s);                                                                \
     }                                                                                                        \
     int col_blocks_##SUF(int nx, int ny) { return col_blocks<T>(nx, ny); }                                   \
+    int plan_radices_##SUF(int n, int* r, int m) { return plan_radices<T>(n, r, m); }                         \
     hipError_t launch_twiddles_##SUF(void* tw, int n, hipStream_t s) { return launch_twiddles<T>(tw, n, s); } \
     hipError_t launch_beam_tables_##SUF(void* bx, void* by, const BeamArgs& b, hipStream_t s)               \
     {                                                                                                        \

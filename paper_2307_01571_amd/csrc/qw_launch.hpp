@@ -52,6 +52,7 @@ struct RowArgs {
     int ny;
     FullBeam full;            // beam_mode == QW_BEAM_GAUSSIAN_FULL_
     const StepClock* clock;   // if set (graph replays): t0 and dt from here, k offset by clock->k_base
+    int one_block;            // ROW_MID: 0 both Dirac blocks, 1 block A only, 2 block B only
 };
 
 struct ColArgs {
@@ -67,6 +68,7 @@ struct ColArgs {
                       // COL_MAPS: [ny][nx][3] per-cell (|phi|^2, |c+|^2, |c-|^2)
     int partial_stride;
     int band_ref, band_half, window, n_max, spin0;
+    int one_block;     // COL_PROP: 0 both Dirac blocks, 1 block A only, 2 block B only
 };
 
 struct BeamArgs {
@@ -127,6 +129,7 @@ struct BatchLaunch {
     hipError_t launch_row_##SUF(int mode, int nx, const RowArgs& a, hipStream_t s);       \
     hipError_t launch_col_##SUF(int mode, int ny, const ColArgs& a, hipStream_t s);       \
     int col_blocks_##SUF(int nx, int ny);                                                 \
+    int plan_radices_##SUF(int n, int* radices, int max_radices);                         \
     hipError_t launch_twiddles_##SUF(void* tw, int n, hipStream_t s);                     \
     hipError_t launch_beam_tables_##SUF(void* bx, void* by, const BeamArgs& b, hipStream_t s); \
     hipError_t launch_packet_##SUF(void* psi, double* rownorm, const PacketArgs& e, hipStream_t s); \

@@ -35,7 +35,8 @@ QW_BEAM_UNIFORM = 2
 QW_BEAM_GAUSSIAN_FULL = 3
 
 EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_set_frame", "qw_init_packet", "qw_step_n",
-            "qw_observables", "qw_momentum_maps", "qw_kernel_timing", "qw_kernel_times", "qw_last_error", "qw_destroy",
+            "qw_observables", "qw_momentum_maps", "qw_kernel_timing", "qw_kernel_times", "qw_transform_gain", "qw_last_error",
+            "qw_destroy",
             "qw_batch_layout", "qw_batch_init", "qw_batch_init_packets", "qw_batch_step_n",
             "qw_batch_observables", "qw_batch_schedule", "qw_batch_set_schedule", "qw_batch_set_launch",
             "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
@@ -111,6 +112,7 @@ def lib():
     L.qw_momentum_maps.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     L.qw_kernel_timing.argtypes = [vp, ctypes.c_int]
     L.qw_kernel_times.argtypes = [vp, dp, ctypes.c_int32, vp]
+    L.qw_transform_gain.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp]
     L.qw_last_error.argtypes = [vp]
     L.qw_last_error.restype = ctypes.c_char_p
     L.qw_destroy.argtypes = [vp]
@@ -226,6 +228,13 @@ def qw_kernel_times(ctx: int, stream: int):
     out = (ctypes.c_double * 4)()
     _check(lib().qw_kernel_times(ctypes.c_void_p(ctx), out, 4, ctypes.c_void_p(stream)), ctx)
     return [float(v) for v in out]
+
+
+def qw_transform_gain(n: int, precision: int, batch_variant: int = -1) -> float:
+    """Modelled mean squared-norm gain of one transform of length n (host arithmetic only)."""
+    out = ctypes.c_double()
+    _check(lib().qw_transform_gain(int(n), int(precision), int(batch_variant), ctypes.byref(out)), None)
+    return out.value
 
 
 def qw_last_error(ctx=None) -> str:

@@ -83,14 +83,13 @@ def test_large_grid_prefix_f64_matches_oracle(name):
 def test_large_grid_prefix_f32_matches_oracle(name):
     """FP32 at 2048^2 in the bench's launch sequence (graph replays plus
     direct launches) against the oracle's sampled cells and observables.
-    Bar: the FP32 path's error grows linearly with the steps: a coherent
-    drift of the norm (about -7e-8 per step with the jointly rounded
-    rotation constants, -2e-7 per step with nearest-rounded ones) plus the
-    phase errors of the same origin, above the rounding noise
-    sqrt(n log2 N) 2^-24.  Measured with the nearest-rounded constants:
-    9.6e-6 relative L2 after 100 steps; the bar, 3e-7 n (3e-5 at 100
-    steps), keeps a factor three over that.  Probabilities (ratios to the
-    current norm, which remove the drift): helpers.fp32_bars."""
+    Bar: the FP32 path's error grows linearly with the steps, a coherent
+    drift of the norm (the nearest-rounded rotation constants lose about
+    2e-7 per step, which the kinetic table's norm factor takes out on
+    average) and of the phases, above the rounding noise sqrt(n log2 N)
+    2^-24.  Measured without the norm factor: 9.6e-6 relative L2 after 100
+    steps; the bar, 3e-7 n (3e-5 at 100 steps), keeps a factor three over
+    that.  Probabilities (ratios to the current norm): helpers.fp32_bars."""
     rec = load(name)
     wl = workload_of(rec)
     sim, obs = run_gpu(wl, qw.QW_F32, rec["steps"], rec["t0"])

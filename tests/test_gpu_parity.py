@@ -205,9 +205,11 @@ def test_split_calls_agree():
 @pytest.mark.parametrize("prec", [F64, F32])
 def test_graph_replays_equal_direct_launches(prec):
     # 150 steps: two replays of the captured 64-step chunk plus 21 direct
-    # steps; with per-launch timing on the loop launches every step
-    # directly.  Same kernels, same step times: bitwise equal states.  Then
-    # a new beam (recapture) and a second state array (another capture).
+    # steps, the middle passes of the two Dirac blocks as two chains on two
+    # streams; with per-launch timing on, the loop launches every pass of
+    # both blocks directly on the one stream.  Same arithmetic, same step
+    # times: bitwise equal states.  Then a new beam (recapture) and a second
+    # state array (another capture).
     wl = W.small_parity()
     print_case(test="graph_replays", prec=prec)
     a = qw.Sim(wl.grid, prec, beam=wl.beam)
@@ -230,6 +232,26 @@ def test_graph_replays_equal_direct_launches(prec):
     a.psi, other = other, a.psi
     a.step(70, 280 * wl.dt, wl.dt)
     b.step(70, 280 * wl.dt, wl.dt)
+    qw.qw_kernel_times(b.ctx, b.stream())
+    assert np.array_equal(a.state(), b.state())
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129])
+def test_block_chains_equal_single_stream(n):
+    # the two-chain loop around the chunk boundaries (no middle step, one,
+    # a chunk less one, a whole chunk, a chunk and one, two chunks and one)
+    # equals the single-stream launches bit for bit
+    wl = W.small_parity()
+    print_case(test="block_chains", n=n)
+    a = qw.Sim(wl.grid, F32, beam=wl.beam)
+    b = qw.Sim(wl.grid, F32, beam=wl.beam)
+    a.init_packet(wl.packet)
+    b.init_packet(wl.packet)
+    qw.qw_kernel_timing(b.ctx, True)
+    a.step(n, 0.0, wl.dt)
+    b.step(n, 0.0, wl.dt)
     qw.qw_kernel_times(b.ctx, b.stream())
     assert np.array_equal(a.state(), b.state())
     a.close()
