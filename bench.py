@@ -458,6 +458,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the surrogate network timing")
     ap.add_argument("--no-unfused", action="store_true",
                     help="skip the torch.fft (rocFFT) comparison of the same step")
+    ap.add_argument("--precision", choices=("f32", "f64"), default="f32",
+                    help="arithmetic of the timed propagation (f64 skips the FP64 comparison leg)")
     ap.add_argument("--record-counters", metavar="DIR",
                     help="write the traffic record from rocprofv3 --pmc runs under DIR (fetch/, write/, sq/, "
                          "copy_fetch/, copy_write/) and exit; runs without a GPU")
@@ -468,6 +470,10 @@ def main():
     if a.record_counters:
         record_counters(a.record_counters)
         return
+    key = a.precision
+    label = key.upper().replace("F", "FP")
+    if key == "f64":
+        a.no_f64 = True  # the timed run is the FP64 one
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the 2048^2 propagation is "
               "measured on a single GPU, with no sharding across GPUs", file=sys.stderr)
@@ -496,31 +502,32 @@ def main():
     # --timing-steps steps, and the plain copy of the state.  Both also bring
     # the GPU to its working clocks, so a short timed region measures the
     # same steady state as a long one.
-    sim32 = qw.Sim(wl.grid, qw.QW_F32, beam=wl.beam)
+    prec = qw.QW_F32 if key == "f32" else qw.QW_F64
+    sim32 = qw.Sim(wl.grid, prec, beam=wl.beam)
     kt = kernel_times(qw, sim32, wl, a.timing_steps, torch)
     copy_us, copy_gbs, _ = copy_rate(torch, wl)
 
-    log(f"FP32 {wl.grid.nx}x{wl.grid.ny}: warmup {a.warmup}, timed {a.steps} steps")
-    sim32, t32, obs32 = run_precision(qw, wl, qw.QW_F32, a.steps, a.warmup, torch, sim=sim32)
+    log(f"{label} {wl.grid.nx}x{wl.grid.ny}: warmup {a.warmup}, timed {a.steps} steps")
+    sim32, t32, obs32 = run_precision(qw, wl, prec, a.steps, a.warmup, torch, sim=sim32)
     value = cells * a.steps / t32
-    log(f"FP32: {t32:.3f} s, {value:.4e} cell-steps/s, {1e3 * t32 / a.steps:.4f} ms/step")
+    log(f"{label}: {t32:.3f} s, {value:.4e} cell-steps/s, {1e3 * t32 / a.steps:.4f} ms/step")
 
     per = {}
     for k, (cnt, ms) in kt.items():
         avg_s = ms / max(cnt, 1) / 1e3
-        gbs = BYTES_PER_CELL_PASS["f32"] * cells / avg_s / 1e9
+        gbs = BYTES_PER_CELL_PASS[key] * cells / avg_s / 1e9
         per[k] = {"launches": int(cnt), "avg_us": avg_s * 1e6, "GBps": gbs}
         log(f"  {k} pass: {cnt:.0f} launches, avg {avg_s * 1e6:.2f} us, {gbs:.0f} GB/s algorithmic")
     dom = max(per, key=lambda k: per[k]["avg_us"])
     dom_name = "col_pass" if dom == "col" else "row_pass"
-    counters = measured_counters(dom_name)
+    counters = measured_counters(dom_name) if key == "f32" else None  # the traffic record is of the FP32 passes
     traffic = None if counters is None else counters["bytes"]
     roofline = {"bound": "hbm", "kernel": dom_name,
                 "achieved": round(per[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(per[dom]["GBps"] / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / (per[dom]["avg_us"] * 1e-6) / 1e9, 1),
                 "traffic_bytes_per_launch": traffic,
-                "bytes_per_launch": BYTES_PER_CELL_PASS["f32"] * cells,
+                "bytes_per_launch": BYTES_PER_CELL_PASS[key] * cells,
                 "avg_launch_us": {k: round(v["avg_us"], 3) for k, v in per.items()},
                 # the timed region as a whole: the two passes' algorithmic
                 # bytes per step over the measured step time.  There the
@@ -528,7 +535,7 @@ def main():
                 # chains of per-block launches, so one kernel's tail overlaps
                 # the other chain's work; the per-launch figures above are of
                 # whole-state launches, one at a time on one stream.
-                "step_GBps": round(2 * BYTES_PER_CELL_PASS["f32"] * cells * a.steps / t32 / 1e9, 1)}
+                "step_GBps": round(2 * BYTES_PER_CELL_PASS[key] * cells * a.steps / t32 / 1e9, 1)}
     roofline["step_frac"] = round(roofline["step_GBps"] / HBM_PEAK_GBS, 4)
     if counters is not None and counters["valu_insts"]:
         # the second limit: wave-level FP32 VALU issue (no packed FP32), one
@@ -643,9 +650,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": key,
         "data": "synthetic",
-        "config": {"workload": "grid2048_box64_w16_a0.5 Strang steps (Dirac split-operator, FP32, "
+        "config": {"workload": f"grid2048_box64_w16_a0.5 Strang steps (Dirac split-operator, {label}, "
                                "FP64 phases and reductions)",
                    "nx": wl.grid.nx, "ny": wl.grid.ny, "box_wavelengths": 64, "w0_wavelengths": 16,
                    "a0": wl.beam.a0, "dt": wl.dt, "steps": a.steps},

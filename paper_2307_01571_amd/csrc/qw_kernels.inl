@@ -22,8 +22,8 @@
 //  - per-lane-group LDS buffer padding in elements (row / column passes);
 //  - columns per workgroup once a column needs >= 128 lanes;
 //  - minimum waves per SIMD the register allocation must allow: 3 for the
-//    float passes (at most 168 VGPRs: three 256-lane workgroups per CU),
-//    2 for the double row passes (two 512-lane workgroups never fit a CU),
+//    float passes (at most 168 VGPRs: three 256-lane workgroups per CU), 2
+//    for the double row passes (two 256-lane workgroups per CU, no spills),
 //    4 for the double column passes.
 #ifndef QW_LDS_EXTRA_ROW
 #define QW_LDS_EXTRA_ROW 8
@@ -111,7 +111,12 @@ struct shape {
     static constexpr int NT = N / E;                                  // lanes per line and block
     static constexpr int L = 2 * NT;                                  // lanes per line
     static constexpr int RPW = L >= 256 ? 1 : 256 / L;                // rows per workgroup
+    static constexpr int RT = NT >= 256 ? 1 : 256 / NT;               // rows of one block per middle row tile
     static constexpr int TX = L >= 512 ? 1 : (L >= 128 ? QW_TX_COL : 256 / L);  // columns per workgroup
+    // columns of one block per middle column tile: two, so a tile reads whole
+    // lines of the split layout (one-column tiles halve the double column
+    // pass's rate at 2048^2: 152 -> 240 us)
+    static constexpr int CT = 2 * TX;
     // per-lane-group LDS buffer strides (elements); the extra elements move
     // the groups' buffers onto different banks
     static constexpr int LLR = lds_len<T, N>::value + QW_LDS_EXTRA_ROW;
@@ -259,25 +264,27 @@ __device__ __forceinline__ uint32_t split_off(int b, int y, int x, int nx, int n
 // One tile of RPW rows of length N (transform with E elements per lane and
 // the radix schedule SCH, LDS stride LL per lane group), threads
 // 0 .. RPW 2 N/E - 1.  lds holds RPW 2 LL elements.  IN and OUT are the
-// layouts read and written.  With both LAY_SPLIT the tile is 2 RPW rows of
-// one block (lane 2q + r: row parity r); otherwise RPW rows of both blocks
-// (lane 2q + b: block b).  Either way lane 2q + j uses LDS group 2 s + j.
+// layouts read and written.  With both LAY_SPLIT the tile is RT rows of one
+// block (RT = shape::RT: 1 when a row takes 256 or more lanes; else lane
+// 2q + r: row parity r); otherwise RPW rows of both blocks (lane 2q + b:
+// block b).  Lane 2q + j uses LDS group 2 s + j (lane t: group 0 if RT = 1).
 template <typename T, int N, int E, typename SCH, int RPW, int LL, int MODE, int BEAM = 0, int IN = LAY_ABI,
           int OUT = LAY_ABI, bool ONE = false>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds, int tid)
 {
     constexpr int NT = N / E, L = 2 * NT;
     constexpr bool SPLIT_MAP = IN == LAY_SPLIT && OUT == LAY_SPLIT;
+    constexpr int RT = SPLIT_MAP ? shape<T, N>::RT : 2 * RPW;
     using G = split_geom<T>;
-    const int lo = tid & 1;
-    const int q = tid >> 1;
+    const int lo = RT >= 2 ? tid & 1 : 0;
+    const int q = RT >= 2 ? tid >> 1 : tid;
     const int s = q / NT;
     const int t = q - s * NT;
     int blk, y;
     if constexpr (SPLIT_MAP) {
-        const int tpb = (a.ny + 2 * RPW - 1) / (2 * RPW);  // tiles per block
+        const int tpb = (a.ny + RT - 1) / RT;  // tiles per block
         blk = ONE ? a.one_block - 1 : (tile >= tpb ? 1 : 0);
-        y = (ONE ? tile : tile - blk * tpb) * 2 * RPW + 2 * s + lo;
+        y = (ONE ? tile : tile - blk * tpb) * RT + 2 * s + lo;
     } else {
         blk = lo;  // 0: (psi1, psi4), 1: (psi3, psi2)
         y = tile * RPW + s;
@@ -387,12 +394,22 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int tile, cx<T>* lds,
 
 // ONE: the launch covers the block a.one_block only (a separate symbol, so a
 // kernel trace tells the per-block launches from the whole-state ones)
+// lane groups (one per row and block, NT lanes and one LDS buffer each) and
+// threads of a row-pass workgroup: the middle passes take RT rows of one
+// block, the others RPW rows of both blocks
+template <typename T, int N, int MODE>
+struct row_wg {
+    using S = shape<T, N>;
+    static constexpr int groups = MODE == ROW_MID ? S::RT : 2 * S::RPW;
+    static constexpr int threads = groups * S::NT;
+};
+
 template <typename T, int N, int MODE, int BEAM = 0, bool ONE = false>
-__global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__((
+__global__ __launch_bounds__((row_wg<T, N, MODE>::threads)) __attribute__((
     amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? QW_WPE_ROW : QW_WPE_ROW_F64))) void row_pass(RowArgs a)
 {
     using S = shape<T, N>;
-    __shared__ cx<T> lds[S::RPW * 2 * S::LLR];
+    __shared__ cx<T> lds[row_wg<T, N, MODE>::groups * S::LLR];
     if (a.clock) {  // a replayed chunk of steps: its time is kept on the device
         a.t0 = a.clock->t0;
         a.dt = a.clock->dt;
@@ -401,16 +418,18 @@ __global__ __launch_bounds__((shape<T, N>::RPW * shape<T, N>::L)) __attribute__(
     // a propagation keeps the split layout from its first row pass to its last
     constexpr int IN = (MODE == ROW_MID || MODE == ROW_LAST) ? LAY_SPLIT : LAY_ABI;
     constexpr int OUT = (MODE == ROW_FIRST || MODE == ROW_MID) ? LAY_SPLIT : LAY_ABI;
-    // Middle passes in float: tiles 2P and 2P + 1 (two rows each) share
-    // every line of the split layout.  Workgroups are dealt round-robin to
-    // the 8 XCDs, so the pair goes to the two workgroups an XCD receives one
-    // after the other (blockIdx b and b + 8): they run together, and the
-    // second reader of each line finds it in that XCD's L2.
+    // Middle passes: when a tile has fewer rows (RT) than a line of the split
+    // layout (LY), the GR = LY / RT tiles GR P .. GR P + GR - 1 share every
+    // line.  Workgroups are dealt round-robin to the 8 XCDs, so the group
+    // goes to the workgroups an XCD receives one after the other (blockIdx
+    // b, b + 8, ...): they run together, and the later readers of each line
+    // find it in that XCD's L2.
     int tile = blockIdx.x;
-    if constexpr (IN == LAY_SPLIT && OUT == LAY_SPLIT && split_geom<T>::LY > 2) {
-        if ((gridDim.x & 15) == 0) {
+    if constexpr (IN == LAY_SPLIT && OUT == LAY_SPLIT && split_geom<T>::LY > S::RT) {
+        constexpr int GR = split_geom<T>::LY / S::RT;
+        if (gridDim.x % (8 * GR) == 0) {
             const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
-            tile = 2 * ((i >> 1) * 8 + x) + (i & 1);
+            tile = GR * ((i / GR) * 8 + x) + i % GR;
         }
     }
     row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM, IN, OUT, ONE>(a, tile, lds, threadIdx.x);
@@ -466,8 +485,9 @@ __device__ __forceinline__ void apply_kinetic(cx<T> (&v)[2][E], const ColArgs& a
     }
 }
 
-// One tile of TX columns of length N, threads 0 .. TX 2 N/E - 1; lds holds
-// TX 2 LL elements.
+// One tile of columns of length N: TX columns of both blocks (LAY_ABI) or
+// CT = shape::CT columns of one block (LAY_SPLIT), NT lanes and one LDS
+// buffer of LL elements per column and block.
 template <typename T, int N, int E, typename SCH, int TX, int LL, int MODE, int FRAME = 0, int LAY = LAY_ABI,
           bool ONE = false>
 __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds, int tid)
@@ -476,29 +496,35 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
     using G = split_geom<T>;
     // LAY_ABI: lane order block fastest, then the column within the tile, then
     // t, so a wave reads TX whole cells of each of several rows.  LAY_SPLIT: a
-    // tile is CT = 2 TX columns of one block, lane order column then t.  Lane
-    // j (mod CT) uses LDS group j either way.
-    constexpr int CT = 2 * TX;
+    // tile is CT columns of one block, lane order column then t.  Lane j (mod
+    // CT) uses LDS group j either way (CT = 2 TX for LAY_ABI).
+    constexpr int CT = LAY == LAY_SPLIT ? shape<T, N>::CT : 2 * TX;
     const int grp = tid & (CT - 1);
     const int t = tid / CT;
     int blk, x;
     if constexpr (LAY == LAY_SPLIT) {
-        // Tile order: in a launch of both blocks, tiles 2j and 2j + 1 are
-        // column group j of blocks A and B; group j is the (j/2)-th group
-        // from the left for even j, from the right for odd j.  Tiles that
-        // follow each other run on one XCD at nearly the same time, so the
-        // rows of the kinetic table they read (indexed by |kx|, shared by
-        // columns x and nx - x and by both blocks) come from that XCD's L2.
-        const int tpb = (a.nx + CT - 1) / CT;  // tiles per block
+        // Tile order: when a tile has fewer columns than a line (LX), the LXT
+        // tiles that share the lines of CW = LX columns follow each other.
+        // In a launch of both blocks, the column groups u = 2j and 2j + 1 are
+        // group j of blocks A and B; group j is the (j/2)-th group from the
+        // left for even j, from the right for odd j.  Tiles that follow each
+        // other run on one XCD at nearly the same time, so the lines they
+        // share, and the rows of the kinetic table they read (indexed by
+        // |kx|, shared by columns x and nx - x and by both blocks), come from
+        // that XCD's L2.
+        constexpr int LXT = G::LX > CT ? G::LX / CT : 1;
+        constexpr int CW = CT * LXT;
+        const int c = tile % LXT, u = tile / LXT;
+        const int tpb = (a.nx + CW - 1) / CW;  // column groups per block
         int j;
         if constexpr (ONE) {
             blk = a.one_block - 1;
-            j = tile;
+            j = u;
         } else {
-            blk = tile & 1;
-            j = tile >> 1;
+            blk = u & 1;
+            j = u >> 1;
         }
-        x = ((j & 1) ? tpb - 1 - (j >> 1) : (j >> 1)) * CT + grp;
+        x = ((j & 1) ? tpb - 1 - (j >> 1) : (j >> 1)) * CW + c * CT + grp;
     } else {
         blk = tid & 1;
         x = tile * TX + (grp >> 1);
@@ -656,12 +682,22 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, int tile, cx<T>* lds,
     }
 }
 
+// lane groups (one per column and block) and threads of a column-pass
+// workgroup: the propagation's passes take CT columns of one block, the
+// others TX columns of both blocks
+template <typename T, int N, int MODE>
+struct col_wg {
+    using S = shape<T, N>;
+    static constexpr int groups = MODE == COL_PROP ? S::CT : 2 * S::TX;
+    static constexpr int threads = groups * S::NT;
+};
+
 template <typename T, int N, int MODE, int FRAME = 0, bool ONE = false>
-__global__ __launch_bounds__((shape<T, N>::TX * shape<T, N>::L)) __attribute__((
+__global__ __launch_bounds__((col_wg<T, N, MODE>::threads)) __attribute__((
     amdgpu_waves_per_eu(sizeof(T) == sizeof(float) ? QW_WPE_COL : QW_WPE_COL_F64))) void col_pass(ColArgs a)
 {
     using S = shape<T, N>;
-    __shared__ cx<T> lds[S::TX * 2 * S::LLC];
+    __shared__ cx<T> lds[col_wg<T, N, MODE>::groups * S::LLC];
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
     // give each XCD a contiguous run of tiles -- neighbouring tiles share
     // cache lines (or kinetic table rows) and then meet in the same L2
@@ -826,11 +862,10 @@ template <typename T, int N>
 hipError_t row_launch_n(int mode, const RowArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
-    // ROW_MID tiles are 2 RPW rows of one block: as many workgroups as RPW
-    // rows of both blocks, or half as many for one block
+    // ROW_MID tiles are RT rows of one block (of both blocks, or of one)
     const int nb = a.one_block ? 1 : 2;
-    const dim3 grid(mode == ROW_MID ? nb * ((a.ny + 2 * S::RPW - 1) / (2 * S::RPW)) : (a.ny + S::RPW - 1) / S::RPW),
-        block(S::RPW * S::L);
+    const dim3 grid(mode == ROW_MID ? nb * ((a.ny + S::RT - 1) / S::RT) : (a.ny + S::RPW - 1) / S::RPW),
+        block(mode == ROW_MID ? row_wg<T, N, ROW_MID>::threads : S::RPW * S::L);
     if (a.beam_mode == QW_BEAM_GAUSSIAN_FULL_) {
         switch (mode) {
         case ROW_FIRST: hipLaunchKernelGGL((row_pass<T, N, ROW_FIRST, 1>), grid, block, 0, st, a); break;
@@ -863,10 +898,10 @@ template <typename T, int N>
 hipError_t col_launch_n(int mode, const ColArgs& a, hipStream_t st)
 {
     using S = shape<T, N>;
-    // COL_PROP tiles are 2 TX columns of one block (of both blocks, or of one)
+    // COL_PROP tiles are CT columns of one block (of both blocks, or of one)
     const int nb = a.one_block ? 1 : 2;
-    const dim3 grid(mode == COL_PROP ? nb * ((a.nx + 2 * S::TX - 1) / (2 * S::TX)) : (a.nx + S::TX - 1) / S::TX),
-        block(S::TX * S::L);
+    const dim3 grid(mode == COL_PROP ? nb * ((a.nx + S::CT - 1) / S::CT) : (a.nx + S::TX - 1) / S::TX),
+        block(mode == COL_PROP ? col_wg<T, N, COL_PROP>::threads : S::TX * S::L);
     switch (mode) {
     case COL_PROP:
         if (a.frame && a.one_block) hipLaunchKernelGGL((col_pass<T, N, COL_PROP, 1, true>), grid, block, 0, st, a);
