@@ -46,16 +46,23 @@ def _log(*a):
     print("[experiments]", *a, file=sys.stderr, flush=True)
 
 
-def setup(kl_mc=0.1, eps=0.02, a0_mc=0.1, nx=2048, ny=128, box_x=80, box_y=40, px_kl=-1.0, longitudinal=1):
-    """Grid, beam, packet, frame and step plan of the showcase family (lengths in lambda)."""
+def setup(kl_mc=0.1, eps=0.02, a0_mc=0.1, nx=2048, ny=128, box_x=80, box_y=40, px_kl=-1.0, longitudinal=1,
+          w0_kl_mc=None, sigma_p_mc=None):
+    """Grid, beam, packet, frame and step plan of the showcase family (lengths in lambda).
+
+    By default every length follows lambda: the box, the start y0 = -140
+    lambda and the travel time, the waist w0 = 1/(k_L eps) and the packet's
+    sigma_p = hbar k_L/200.  w0_kl_mc fixes the waist at 1/(k eps) with k =
+    w0_kl_mc m c/hbar whatever k_L; sigma_p_mc fixes sigma_p in m c."""
     kl = kl_mc * C
     lam = 2 * math.pi / kl
     lam_c = 2 * math.pi / C
     g = W.GridSpec(nx=nx, ny=ny, x_min=-box_x / 2 * lam, y_min=(-140 - box_y / 2) * lam, lx=box_x * lam,
                    ly=box_y * lam)
-    b = W.BeamSpec(mode=qw.QW_BEAM_GAUSSIAN_FULL, a0=a0_mc * C, lambda_l=lam, w0=1.0 / (kl * eps), ramp_periods=0.0,
+    k_w0 = kl if w0_kl_mc is None else w0_kl_mc * C
+    b = W.BeamSpec(mode=qw.QW_BEAM_GAUSSIAN_FULL, a0=a0_mc * C, lambda_l=lam, w0=1.0 / (k_w0 * eps), ramp_periods=0.0,
                    longitudinal=longitudinal)
-    sigma_p = kl / 200
+    sigma_p = kl / 200 if sigma_p_mc is None else sigma_p_mc * C
     p = W.PacketSpec(p0x=px_kl * kl, p0y=C, x0=140 * lam_c, y0=-140 * lam, sigma_x=1 / (2 * sigma_p), spin=1)
     dt = 0.05 / C ** 2
     steps = int(round(280 * lam * math.sqrt(2) / C / dt))
@@ -164,21 +171,37 @@ def showcase(prec=qw.QW_F64, **kw):
             "peak_minus_k_c_plus_sq": c0p / total}
 
 
-def scaling(prec=qw.QW_F32, eps_list=(0.01, 0.02, 0.05, 0.1), kl_list=(0.05, 0.07, 0.1), longitudinal_off=False):
-    """The scan's runs of one k_L go together (equal step counts)."""
+# Readings of the scan's parameters (which lengths follow lambda = 2 pi/k_L):
+#   scaled      every length follows lambda (box, y0, travel time, w0 = 1/(k_L eps), sigma_p = hbar k_L/200)
+#   fixed_w0    as scaled, but w0 = 1/(k eps) with k = 0.1 m c/hbar for every k_L
+#   fixed_sigma as scaled, but sigma_p = 0.1 m c/200 for every k_L
+READINGS = {"scaled": {}, "fixed_w0": {"w0_kl_mc": 0.1}, "fixed_sigma": {"sigma_p_mc": 0.1 / 200}}
+
+
+def scaling(prec=qw.QW_F32, eps_list=(0.01, 0.02, 0.05, 0.1), kl_list=(0.05, 0.07, 0.1), longitudinal_off=False,
+            reading="scaled"):
+    """The scan's runs of one k_L go together (equal step counts).  Each row
+    has the spin-flip density at the diffracted peak as a share of the total
+    (c_minus_sq) and the areas of one grid cell in momentum and position
+    space, which turn the share into other normalisations of |phi|^2."""
     rows = []
+    extra = READINGS[reading]
     for kl in kl_list:
         cfgs, keys = [], []
         for eps in eps_list:
             for lon in ((1, 0) if longitudinal_off else (1,)):
-                cfgs.append(setup(kl_mc=kl, eps=eps, longitudinal=lon))
+                cfgs.append(setup(kl_mc=kl, eps=eps, longitudinal=lon, **extra))
                 keys.append((eps, lon))
         _log(f"scaling: k_L = {kl} m c, {len(cfgs)} runs of {cfgs[0]['steps']} steps")
         for (eps, lon), cfg, (obs, maps, el) in zip(keys, cfgs, run_many(cfgs, prec)):
             total = float(np.sum(maps[..., 0]))
             cp, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=1)
             cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
-            rows.append({"kl_mc": kl, "eps": eps, "longitudinal": lon, "steps": cfg["steps"], "group_seconds": el,
+            g = cfg["grid"]
+            rows.append({"reading": reading, "kl_mc": kl, "eps": eps, "longitudinal": lon, "steps": cfg["steps"],
+                         "group_seconds": el, "w0": cfg["beam"].w0, "sigma_x": cfg["packet"].sigma_x,
+                         "cell_area_p": (2 * math.pi) ** 2 / (g.lx * g.ly), "cell_area_r": g.lx * g.ly / (g.nx * g.ny),
+                         "cells": g.nx * g.ny,
                          "c_plus_sq": cp / total, "c_minus_sq": cm / total,
                          "P_plus1": float(obs["P"][cfg["obs"].n_max + 1]),
                          "P_plus1_plus": float(obs["Pp"][cfg["obs"].n_max + 1]),
@@ -213,11 +236,20 @@ def diffraction(prec=qw.QW_F64, px_kl=-1.0, n_orders=(-3, -2, -1, 0, 1, 2, 3)):
         sub = maps[:, cols, 0]
         jj, ii = np.unravel_index(int(np.argmax(sub)), sub.shape)
         pop = float(obs["P"][o.n_max + n]) if abs(n) <= o.n_max else None
+        # the local maxima of |c+|^2 and |c-|^2 around the Eq. 22 location
+        # (p_x0 + 2 n hbar k_L, m c + Delta p_y): within 10 cells in p_x and
+        # 8 cells in p_y, as the largest value of each projection at the peak
+        iy22 = int(np.argmin(np.abs(py - (C + est))))
+        near_x = [(ix + d) % len(px) for d in range(-10, 11)]
+        near_y = [(iy22 + d) % len(py) for d in range(-8, 9)]
+        box = maps[np.ix_(near_y, near_x)]
         rows.append({"n": n, "band_P": pop, "peak_density": float(col[j]) / total, "dpy_measured": dpy,
                      "dpy_eq22": est, "dpy_cell": float(2 * math.pi / cfg["grid"].ly),
                      "window_peak_density": float(sub[jj, ii]) / total,
                      "window_peak_at": [float(px[cols[ii]] / kl), float((py[jj] - C) / kl)],
-                     "c_plus_sq": float(maps[j, ix, 1]) / total, "c_minus_sq": float(maps[j, ix, 2]) / total})
+                     "c_plus_sq": float(maps[j, ix, 1]) / total, "c_minus_sq": float(maps[j, ix, 2]) / total,
+                     "c_plus_sq_localmax": float(box[..., 1].max()) / total,
+                     "c_minus_sq_localmax": float(box[..., 2].max()) / total})
     return {"px_kl": px_kl, "seconds": el, "orders": rows,
             "bands": {k: (list(map(float, v)) if isinstance(v, np.ndarray) else v) for k, v in obs.items()}}
 
@@ -228,13 +260,16 @@ def main(argv=None):
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--out", required=True)
     ap.add_argument("--kl", type=float, nargs="+", default=[0.05, 0.07, 0.1], help="hbar k_L / (m c) of the scans")
+    ap.add_argument("--eps", type=float, nargs="+", default=[0.01, 0.02, 0.05, 0.1], help="beam divergences of the scans")
+    ap.add_argument("--reading", choices=sorted(READINGS), default="scaled",
+                    help="which lengths of the scans follow the laser wavelength")
     a = ap.parse_args(argv)
     qw.lib()
     prec = qw.QW_F64 if a.prec == "f64" else qw.QW_F32
     if a.what == "showcase":
         res = showcase(prec)
     elif a.what == "scaling":
-        rows = scaling(prec, kl_list=a.kl)
+        rows = scaling(prec, eps_list=a.eps, kl_list=a.kl, reading=a.reading)
         res = {"rows": rows}
         for kl in sorted({r["kl_mc"] for r in rows}):
             sel = [r for r in rows if r["kl_mc"] == kl]
@@ -245,7 +280,7 @@ def main(argv=None):
                 res[f"slope_vs_kl_eps{eps}"] = loglog_slope([r["kl_mc"] for r in sel],
                                                             [r["c_minus_sq"] for r in sel])
     elif a.what == "longitudinal":
-        rows = scaling(prec, kl_list=a.kl, longitudinal_off=True)
+        rows = scaling(prec, eps_list=a.eps, kl_list=a.kl, longitudinal_off=True, reading=a.reading)
         res = {"rows": rows}
         for kl in sorted({r["kl_mc"] for r in rows}):
             d = []
