@@ -335,7 +335,9 @@ def learned_section(qw, W, torch, batch=4096, reps=50):
     return {"train_step_us": step_s * 1e6, "batch": batch, "nets": s["n_nets"], "train_step_flops": flops,
             "roofline": {"bound": "mfma", "achieved": round(flops / step_s / 1e12, 2), "peak": 2500.0,
                          "unit": "TFLOP/s", "frac": flops / step_s / 1e12 / 2500.0,
-                         "note": "27 small launches per step: latency-bound, not MFMA-bound"},
+                         "note": "23 launches of small products per step; the kernels' own durations add up to "
+                                 "the step time (measured with rocprofv3), so the step is bound by the products' "
+                                 "operand loads and epilogue stores, not by launch gaps"},
             "predict_us": {k: v * 1e6 for k, v in lat.items()}}
 
 

@@ -363,14 +363,16 @@ hipError_t weight_grad(qw_mlp h, int l, const __bf16* dzt, long long s_dzt, cons
         g.Cp = at<float>(h, p.Kp);
         g.sCp_net = p.kp_net;
         e = qwm::launch_gemm(qwm::EPI_PARTIAL, g, p.s.n_nets, y.n_in, s);
+        // the parts' sum and the bias gradient (row sums of dZ^T) in one launch
         if (e == hipSuccess)
-            e = qwm::launch_ksum(g.Cp, p.kp_net, ks, y.n_out, y.n_in, dw, p.np, y.n_in, p.s.n_nets, s);
-    } else {
-        g.Cf = dw;
-        g.sCf = p.np;
-        g.ldcf = y.n_in;
-        e = qwm::launch_gemm(qwm::EPI_F32, g, p.s.n_nets, y.n_in, s);
+            e = qwm::launch_ksum_rows(g.Cp, p.kp_net, ks, y.n_out, y.n_in, dw, p.np, y.n_in, dzt, s_dzt, Mp, y.n_out,
+                                      B, at<float>(h, p.G) + y.b_off, p.np, p.s.n_nets, s);
+        return e;
     }
+    g.Cf = dw;
+    g.sCf = p.np;
+    g.ldcf = y.n_in;
+    e = qwm::launch_gemm(qwm::EPI_F32, g, p.s.n_nets, y.n_in, s);
     if (e == hipSuccess)
         e = qwm::launch_row_sums(dzt, s_dzt, Mp, y.n_out, B, at<float>(h, p.G) + y.b_off, p.np, p.s.n_nets, s);
     return e;

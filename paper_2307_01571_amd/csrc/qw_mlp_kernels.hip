@@ -274,6 +274,47 @@ __global__ __launch_bounds__(256) void ksum(const float* part, long long s_part_
     C[net * s_c + (size_t)m * ldc + n] = acc;
 }
 
+// ksum and row_sums in one launch: workgroups [0, nk) of each net do the
+// split-K sum, the next `rows` workgroups the row sums (same arithmetic)
+__global__ __launch_bounds__(256) void ksum_rows(const float* part, long long s_part_net, int ksplit, int M, int N,
+                                                 float* C, long long s_c, int ldc, int nk, const __bf16* in,
+                                                 long long s_in, int ld, int Mrows, float* out, long long s_out)
+{
+    __shared__ float red[256];
+    const int net = blockIdx.y;
+    if ((int)blockIdx.x < nk) {
+        const int i = blockIdx.x * blockDim.x + threadIdx.x;
+        if (i >= M * N) return;
+        const float* p = part + net * s_part_net + i;
+        float acc = 0.0f;
+        for (int sp = 0; sp < ksplit; ++sp) acc += p[(size_t)sp * M * N];
+        const int m = i / N, n = i - m * N;
+        C[net * s_c + (size_t)m * ldc + n] = acc;
+        return;
+    }
+    const int r = blockIdx.x - nk;
+    const __bf16* row = in + net * s_in + (size_t)r * ld;
+    float sum = 0.0f;
+    for (int m = threadIdx.x; m < Mrows; m += 256) sum += (float)row[m];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[net * s_out + r] = red[0];
+}
+
+hipError_t launch_ksum_rows(const float* part, long long s_part_net, int ksplit, int M, int N, float* C,
+                            long long s_c, int ldc, const __bf16* in, long long s_in, int ld, int rows, int Mrows,
+                            float* out, long long s_out, int nets, hipStream_t s)
+{
+    const int nk = (M * N + 255) / 256;
+    hipLaunchKernelGGL(ksum_rows, dim3(nk + rows, nets), dim3(256), 0, s, part, s_part_net, ksplit, M, N, C, s_c, ldc,
+                       nk, in, s_in, ld, Mrows, out, s_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_ksum(const float* part, long long s_part_net, int ksplit, int M, int N, float* C, long long s_c,
                        int ldc, int nets, hipStream_t s)
 {

@@ -83,6 +83,10 @@ hipError_t launch_gemm(int epi, const GemmArgs& g, int nets, int ncover, hipStre
 // C[net][m][ldc] = sum over split (in order) of part[net][split][m][N]
 hipError_t launch_ksum(const float* part, long long s_part_net, int ksplit, int M, int N, float* C, long long s_c,
                        int ldc, int nets, hipStream_t s);
+// launch_ksum and launch_row_sums(in, s_in, ld, rows, Mrows, out, s_out) as one launch
+hipError_t launch_ksum_rows(const float* part, long long s_part_net, int ksplit, int M, int N, float* C,
+                            long long s_c, int ldc, const __bf16* in, long long s_in, int ld, int rows, int Mrows,
+                            float* out, long long s_out, int nets, hipStream_t s);
 hipError_t launch_prep_input(const float* x, int B, int n_in, int Mpad, const float* shift, const float* scale,
                              __bf16* xb, __bf16* xt, hipStream_t s);
 hipError_t launch_row_sums(const __bf16* in, long long s_in, int ld, int rows, int M, float* out, long long s_out,
