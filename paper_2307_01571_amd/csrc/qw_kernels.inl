@@ -418,15 +418,17 @@ __global__ __launch_bounds__((row_wg<T, N, MODE>::threads)) __attribute__((
     // a propagation keeps the split layout from its first row pass to its last
     constexpr int IN = (MODE == ROW_MID || MODE == ROW_LAST) ? LAY_SPLIT : LAY_ABI;
     constexpr int OUT = (MODE == ROW_FIRST || MODE == ROW_MID) ? LAY_SPLIT : LAY_ABI;
-    // Middle passes: when a tile has fewer rows (RT) than a line of the split
-    // layout (LY), the GR = LY / RT tiles GR P .. GR P + GR - 1 share every
-    // line.  Workgroups are dealt round-robin to the 8 XCDs, so the group
-    // goes to the workgroups an XCD receives one after the other (blockIdx
-    // b, b + 8, ...): they run together, and the later readers of each line
-    // find it in that XCD's L2.
+    // Passes that read or write the split layout: when a tile has fewer rows
+    // (RT rows of one block in the middle passes, RPW rows of both blocks in
+    // the first and last) than a line of the split layout (LY), the GR = LY /
+    // rows tiles GR P .. GR P + GR - 1 share every line.  Workgroups are
+    // dealt round-robin to the 8 XCDs, so the group goes to the workgroups
+    // an XCD receives one after the other (blockIdx b, b + 8, ...): they run
+    // together, and the lines they share meet in that XCD's L2.
+    constexpr int TROWS = (IN == LAY_SPLIT && OUT == LAY_SPLIT) ? S::RT : S::RPW;
     int tile = blockIdx.x;
-    if constexpr (IN == LAY_SPLIT && OUT == LAY_SPLIT && split_geom<T>::LY > S::RT) {
-        constexpr int GR = split_geom<T>::LY / S::RT;
+    if constexpr ((IN == LAY_SPLIT || OUT == LAY_SPLIT) && split_geom<T>::LY > TROWS) {
+        constexpr int GR = split_geom<T>::LY / TROWS;
         if (gridDim.x % (8 * GR) == 0) {
             const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
             tile = GR * ((i / GR) * 8 + x) + i % GR;
