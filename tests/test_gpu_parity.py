@@ -94,8 +94,11 @@ def test_observables_specs_match_oracle(n_max, spin0, window, ref_shift):
     assert np.max(np.abs(got - ref)) <= 1e-13, float(np.max(np.abs(got - ref)))
 
 
+# (2048, 32) and (4096, 32): long rows with one-row middle tiles whose line
+# groups are dealt to one XCD (grids that are multiples of 8 x group size)
 SIZES = [(8, 8), (16, 8), (8, 16), (32, 64), (64, 32), (128, 8), (8, 128), (256, 16), (16, 256),
-         (512, 8), (8, 512), (1024, 8), (8, 1024), (2048, 8), (8, 2048), (4096, 8), (8, 4096)]
+         (512, 8), (8, 512), (1024, 8), (8, 1024), (2048, 8), (8, 2048), (4096, 8), (8, 4096), (2048, 32),
+         (4096, 32)]
 
 
 @pytest.mark.parametrize("nx,ny", SIZES)
@@ -113,7 +116,7 @@ def test_steps_all_sizes_f64(nx, ny):
 
 
 @pytest.mark.parametrize("nx,ny", [(8, 8), (64, 32), (256, 16), (16, 256), (2048, 8), (8, 2048),
-                                   (4096, 8), (8, 4096)])
+                                   (4096, 8), (8, 4096), (2048, 32), (4096, 32)])
 def test_steps_all_sizes_f32(nx, ny):
     print_case(test="steps_f32", nx=nx, ny=ny)
     g = box(nx, ny)
