@@ -424,14 +424,17 @@ __global__ __launch_bounds__((row_wg<T, N, MODE>::threads)) __attribute__((
     // rows tiles GR P .. GR P + GR - 1 share every line.  Workgroups are
     // dealt round-robin to the 8 XCDs, so the group goes to the workgroups
     // an XCD receives one after the other (blockIdx b, b + 8, ...): they run
-    // together, and the lines they share meet in that XCD's L2.
+    // together, and the lines they share meet in that XCD's L2.  Each XCD
+    // takes a contiguous run of groups (rows 2048^2 FP32: 57.8 -> 56.8 us
+    // against groups dealt round-robin).
     constexpr int TROWS = (IN == LAY_SPLIT && OUT == LAY_SPLIT) ? S::RT : S::RPW;
     int tile = blockIdx.x;
     if constexpr ((IN == LAY_SPLIT || OUT == LAY_SPLIT) && split_geom<T>::LY > TROWS) {
         constexpr int GR = split_geom<T>::LY / TROWS;
         if (gridDim.x % (8 * GR) == 0) {
             const int x = blockIdx.x & 7, i = blockIdx.x >> 3;
-            tile = GR * ((i / GR) * 8 + x) + i % GR;
+            const int per = gridDim.x / (8 * GR);  // groups per XCD
+            tile = GR * (x * per + i / GR) + i % GR;
         }
     }
     row_tile<T, N, S::E, typename plan<T, N>::S, S::RPW, S::LLR, MODE, BEAM, IN, OUT, ONE>(a, tile, lds, threadIdx.x);
