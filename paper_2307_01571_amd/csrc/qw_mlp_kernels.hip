@@ -50,26 +50,50 @@ __global__ __launch_bounds__(256) void gemm_nt(GemmArgs g)
     const int n0 = blockIdx.y * 64 + (w & 1) * 32;
     const __bf16* A = g.A + net * g.sA;
     const __bf16* B = g.B + net * g.sB;
-    const int ra = m0 + (lane & 31), rb = n0 + (lane & 31), kl = 8 * (lane >> 5);
+    const int kl = 8 * (lane >> 5);
     const int kbeg = EPI == EPI_PARTIAL ? split * g.k_chunk : 0;
     const int kend = EPI == EPI_PARTIAL ? min(g.K, kbeg + g.k_chunk) : g.K;
 
+    // K in chunks of 64 through LDS, double-buffered: the workgroup loads the
+    // A and B tiles of a chunk (64 rows x 128 bytes each) row-contiguously,
+    // 16 bytes per lane, eight lanes per row, while the waves' products run
+    // on the chunk before; each wave then reads its MFMA operands (8 values
+    // of a row, as before) from LDS.  The products run in the same order as
+    // a direct K loop in steps of 16.
+    __shared__ __bf16 sA[2][64][72], sB[2][64][72];  // row stride 144 bytes
+    const int lr = threadIdx.x >> 3, ls = (threadIdx.x & 7) * 8;
+    const int mt = blockIdx.x * 64, nt = blockIdx.y * 64;
+    bf16x8 ga[2], gb[2];
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool kin = kc + ls < kend;
+            ga[h] = kin ? load_row8(A, mt + lr + 32 * h, g.M, g.lda, kc + ls) : bf16x8{};
+            gb[h] = kin ? load_row8(B, nt + lr + 32 * h, g.N, g.ldb, kc + ls) : bf16x8{};
+        }
+    };
     f32x16 acc = {};
-    int k = kbeg;
-    for (; k + 64 <= kend; k += 64) {
-        bf16x8 a[4], b[4];
+    const int wa = (w >> 1) * 32 + (lane & 31), wb = (w & 1) * 32 + (lane & 31);
+    int buf = 0;
+    if (kbeg < kend) gload(kbeg);
+    for (int kc = kbeg; kc < kend; kc += 64) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<bf16x8*>(&sA[buf][lr + 32 * h][ls]) = ga[h];
+            *reinterpret_cast<bf16x8*>(&sB[buf][lr + 32 * h][ls]) = gb[h];
+        }
+        __syncthreads();
+        if (kc + 64 < kend) gload(kc + 64);
+        const int steps = min(4, (kend - kc) / 16);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            a[u] = load_row8(A, ra, g.M, g.lda, k + 16 * u + kl);
-            b[u] = load_row8(B, rb, g.N, g.ldb, k + 16 * u + kl);
+            if (u < steps) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[buf][wa][16 * u + kl]);
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[buf][wb][16 * u + kl]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b[u], acc, 0, 0, 0);
-    }
-    for (; k < kend; k += 16) {
-        const bf16x8 a = load_row8(A, ra, g.M, g.lda, k + kl);
-        const bf16x8 b = load_row8(B, rb, g.N, g.ldb, k + kl);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        buf ^= 1;
     }
 
     const int n = n0 + (lane & 31);
