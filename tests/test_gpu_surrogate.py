@@ -82,7 +82,7 @@ def test_trained_surrogate_with_fallback():
     assert used[-2:].all()
     ref = S.solve(q)
     assert np.all(np.abs(out[used] - ref[used]) == 0)
-    lat = S.latency(net, x[held][:4], reps=5)
+    lat = S.latency(net, x[held][:4], reps=20)
     print("  latency:", lat)
     assert lat["speedup_1_query"] > 100
     net.close()
