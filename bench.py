@@ -245,6 +245,10 @@ def batch_section(qw, W, torch, steps, single_steps):
     for kind, pass_ in ((2, "row"), (3, "col")):
         cand = [(r[3], int(r[1])) for r in rows if int(r[0]) == kind]
         launches[pass_ + "_wg_per_cu"] = min(cand)[1] if cand else 0
+    # middle steps: graph replays (0) against the step loop (k workgroups per CU)
+    middle = {("graph" if int(r[1]) == 0 else f"loop_{int(r[1])}"): round(r[3], 2) for r in rows if int(r[0]) == 4}
+    cand = [(r[3], int(r[1])) for r in rows if int(r[0]) == 4]
+    launches["loop_wg_per_cu"] = min(cand)[1] if cand else 0
     bt.init_packets([w.packet for w in wls])
     bt.step(20, 0.0, W.DT)
     bt.init_packets([w.packet for w in wls])
@@ -283,9 +287,48 @@ def batch_section(qw, W, torch, steps, single_steps):
             "single_value": single, "single_steps": single_steps,
             "speedup_batched_vs_single": value / single,
             "avg_launch_us": {"row": round(row_us, 2), "col": round(col_us, 2)},
+            "middle_step_us_autotune": middle,
+            "small_batch": loop_small(qw, W, torch),
             "pass_GBps": {"row": round(64 * cells / (row_us * 1e-6) / 1e9, 1),
                           "col": round(64 * cells / (col_us * 1e-6) / 1e9, 1)},
             "schedules": chosen, "launch": launches}
+
+
+def loop_small(qw, W, torch, n_inst=8, n=256, steps=641):
+    """A launch-bound batch (8 instances of 256^2 FP32): microseconds per step
+    with graph replays and with the step loop at every workgroup count per CU
+    that fits, and whether the final states agree bit for bit."""
+    import numpy as np
+    cases = []
+    for i in range(n_inst):
+        g = W.square_box(n, n // 32)
+        cases.append((g, W.BeamSpec(a0=0.3 + 0.1 * i, w0=2.0 * W.LAMBDA_L, ramp_periods=0.0),
+                      W.PacketSpec(sigma_x=1.0)))
+    out, ref = {}, None
+    fit = 0
+    for loop in range(0, 3):
+        bt = qw.Batch([(g, b) for g, b, _ in cases], qw.QW_F32)
+        fit = bt.set_loop(-1)
+        if loop > fit:
+            bt.close()
+            break
+        bt.set_loop(loop)
+        bt.init_packets([p for _, _, p in cases])
+        bt.step(steps, 0.0, W.DT)
+        bt.init_packets([p for _, _, p in cases])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.step(steps, 0.0, W.DT)
+        torch.cuda.synchronize()
+        us = 1e6 * (time.perf_counter() - t0) / steps
+        st = [bt.state(i) for i in range(n_inst)]
+        bt.observables([W.obs_for(g, p, spin0=p.spin) for g, _, p in cases])  # raises if a barrier wait failed
+        bt.close()
+        same = None if ref is None else all(np.array_equal(a, b) for a, b in zip(st, ref))
+        ref = st if ref is None else ref
+        out["graph" if loop == 0 else f"loop_{loop}"] = {"us_per_step": round(us, 2), "bitwise_equal": same}
+    log(f"batch: small batch {n_inst}x{n}^2 {out}")
+    return {"workload": f"{n_inst} instances of {n}^2 FP32, {steps} steps", "loop_fits_per_cu": fit, **out}
 
 
 def learned_section(qw, W, torch, batch=4096, reps=50):

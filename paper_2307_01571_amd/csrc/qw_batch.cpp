@@ -17,6 +17,7 @@
 
 #include "qw.h"
 #include "qw_host.hpp"
+#include "qw_batch_loop.hpp"
 #include "qw_launch.hpp"
 
 namespace {
@@ -53,6 +54,16 @@ struct Prec {
         return f32 ? qw::launch_batch_col_f32(mode, grid, persist, b, s)
                    : qw::launch_batch_col_f64(mode, grid, persist, b, s);
     }
+    int loop_blocks_per_cu() const
+    {
+        return f32 ? qw::batch_loop_blocks_per_cu_f32() : qw::batch_loop_blocks_per_cu_f64();
+    }
+    hipError_t loop(int grid, const qw::BatchLaunch& c, const qw::BatchLaunch& r, int steps, qw::BatchSync* sync,
+                    unsigned long long ticks, hipStream_t s) const
+    {
+        return f32 ? qw::launch_batch_loop_f32(grid, c, r, steps, sync, ticks, s)
+                   : qw::launch_batch_loop_f64(grid, c, r, steps, sync, ticks, s);
+    }
     hipError_t beam(void* bx, void* by, const qw::BeamArgs& a, hipStream_t s) const
     {
         return f32 ? qw::launch_beam_tables_f32(bx, by, a, s) : qw::launch_beam_tables_f64(bx, by, a, s);
@@ -86,7 +97,7 @@ int n_variants(const Prec& p, int lg)
 struct BatchLayout {
     std::vector<int64_t> state_off;
     size_t state_bytes = 0;
-    size_t time = 0, desc = 0, row_items = 0, col_items = 0, scalars = 0, rownorm = 0, partial = 0, plane = 0;
+    size_t time = 0, sync = 0, desc = 0, row_items = 0, col_items = 0, scalars = 0, rownorm = 0, partial = 0, plane = 0;
     std::map<std::pair<int, int>, size_t> tw;             // (lg, variant) -> twiddle table
     std::vector<size_t> bx, by;                           // per instance field tables
     std::map<std::tuple<int, int, double, double, double>, size_t> ktab;  // (nx, ny, lx, ly, c) -> table
@@ -183,6 +194,7 @@ int make_batch_layout(const qw_instance* inst, int n, BatchLayout* L, std::strin
         return at;
     };
     L->time = take(sizeof(qw::StepClock));
+    L->sync = take(sizeof(qw::BatchSync));
     L->desc = take(sizeof(qw::BatchInst) * (size_t)n);
     L->row_items = take(sizeof(uint32_t) * L->row_items_h.size());
     L->col_items = take(sizeof(uint32_t) * L->col_items_h.size());
@@ -234,6 +246,10 @@ struct qw_batch_s {
     int row_var[kMaxLg + 1] = {};
     int col_var[kMaxLg + 1] = {};
     int row_wg_per_cu = 0, col_wg_per_cu = 0, graph_steps = kDefaultGraphSteps;
+    // step loop: workgroups per CU (0: off) and the bound of a barrier wait in wall-clock ticks
+    int loop_wg_per_cu = 0;
+    double wall_khz = 1e5;
+    unsigned long long spin_ticks = 200000000ull;
     bool ktab_valid = false;
     double ktab_dt = 0.0;
     // captured step-loop graph and what it was captured for
@@ -274,6 +290,7 @@ int bhip(qw_batch b, hipError_t e, const char* what)
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 qw::StepClock* dev_time(qw_batch b) { return reinterpret_cast<qw::StepClock*>(b->ws + b->lay.time); }
+qw::BatchSync* dev_sync(qw_batch b) { return reinterpret_cast<qw::BatchSync*>(b->ws + b->lay.sync); }
 qw::BatchInst* dev_desc(qw_batch b) { return reinterpret_cast<qw::BatchInst*>(b->ws + b->lay.desc); }
 
 // Destroys the captured step loop after waiting for its last replay, which
@@ -452,6 +469,42 @@ hipError_t ensure_graph(qw_batch b, char* psi)
     return hipSuccess;
 }
 
+// steps k .. k + count - 1 as one step-loop launch
+hipError_t loop_launch(qw_batch b, char* psi, int64_t k, int count, hipStream_t s)
+{
+    const qw::BatchLaunch c = launch_cols(b, psi);
+    qw::BatchLaunch r = launch_rows(b, psi, psi);
+    r.j = (int)k;
+    r.use_counter = 0;
+    r.tau_frac = 1.0;
+    const int items = std::max(c.n_items, r.n_items);
+    const int grid = std::max(8, std::min(b->loop_wg_per_cu * b->n_cu, (items + 7) / 8 * 8) / 8 * 8);
+    return b->p.loop(grid, c, r, count, dev_sync(b), b->spin_ticks, s);
+}
+
+// Middle steps k .. end - 1 (the device clock holds t0, dt and k_base = k).
+// fast: step-loop launches when the loop is on, else graph replays of
+// graph_steps steps while enough remain; the rest, and everything when not
+// fast, as direct launches.
+hipError_t run_middle(qw_batch b, char* psi, int64_t k, int64_t end, bool fast, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (fast && b->loop_wg_per_cu > 0) {
+        const int chunk = b->graph_steps > 0 ? b->graph_steps : kDefaultGraphSteps;
+        for (; k < end && e == hipSuccess; k += chunk) e = loop_launch(b, psi, k, (int)std::min<int64_t>(chunk, end - k), s);
+        return e;
+    }
+    if (fast && b->graph_steps > 0 && end - k >= b->graph_steps) {
+        e = ensure_graph(b, psi);
+        const int64_t chunks = (end - k) / b->graph_steps;
+        for (int64_t c = 0; c < chunks && e == hipSuccess; ++c) e = hipGraphLaunch(b->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(b->exec_done, s);
+        k += chunks * b->graph_steps;
+    }
+    for (; k < end && e == hipSuccess; ++k) e = middle_step(b, psi, (int)k, false, s);
+    return e;
+}
+
 int check_psi(qw_batch b, const void* psi)
 {
     if (!b) return bfail(nullptr, QW_E_ARG, "batch is NULL");
@@ -509,6 +562,10 @@ int qw_batch_init(qw_batch* out, const qw_instance* inst, int32_t n, void* works
     int cu = 0;
     if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cu > 0)
         b->n_cu = cu;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) == hipSuccess && khz > 0)
+        b->wall_khz = khz;
+    b->spin_ticks = (unsigned long long)(2.0 * 1e3 * b->wall_khz);
     hipStream_t s = as_stream(hip_stream);
     const BatchLayout& Y = b->lay;
     // descriptors
@@ -547,6 +604,7 @@ int qw_batch_init(qw_batch* out, const qw_instance* inst, int32_t n, void* works
         e = hipMemcpyAsync(b->ws + Y.col_items, Y.col_items_h.data(), sizeof(uint32_t) * Y.col_items_h.size(),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = qw::launch_clock_set(dev_time(b), 0.0, 0.0, 0, s);
+    if (e == hipSuccess) e = hipMemsetAsync(dev_sync(b), 0, sizeof(qw::BatchSync), s);
     if (e == hipSuccess) e = upload_desc(b, s);  // waits for the stream
     if (e != hipSuccess) {
         bfail(nullptr, QW_E_DEVICE, "batch set-up: %s", hipGetErrorString(e));
@@ -606,23 +664,16 @@ int qw_batch_step_n(qw_batch b, void* psi, int64_t n, double t0, double dt, void
     r.j = 0;
     r.tau_frac = 0.5;
     if (e == hipSuccess) e = timed(b, 0, s, [&] { return row_pass(b, qw::ROW_FIRST, r, s); });
-    int64_t k = 1;
     // a caller capturing its own stream (or a stream whose state cannot be
     // queried) gets the plain launches
-    bool replay = !b->timing && b->graph_steps > 0 && n - 1 >= b->graph_steps;
+    bool fast = !b->timing;
     hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
-    if (replay && hipStreamIsCapturing(s, &cap_status) != hipSuccess) {
+    if (fast && hipStreamIsCapturing(s, &cap_status) != hipSuccess) {
         (void)hipGetLastError();
-        replay = false;
+        fast = false;
     }
-    if (e == hipSuccess && replay && cap_status == hipStreamCaptureStatusNone) {
-        e = ensure_graph(b, base);
-        const int64_t chunks = (n - 1) / b->graph_steps;
-        for (int64_t c = 0; c < chunks && e == hipSuccess; ++c) e = hipGraphLaunch(b->exec, s);
-        if (e == hipSuccess) e = hipEventRecord(b->exec_done, s);
-        k += chunks * b->graph_steps;
-    }
-    for (; k < n && e == hipSuccess; ++k) e = middle_step(b, base, (int)k, false, s);
+    fast = fast && cap_status == hipStreamCaptureStatusNone;
+    if (e == hipSuccess) e = run_middle(b, base, 1, n, fast, s);
     if (e == hipSuccess) e = timed(b, 1, s, [&] { return col_pass(b, qw::COL_PROP, launch_cols(b, base), s); });
     r.j = (int)n;
     if (e == hipSuccess) e = timed(b, 0, s, [&] { return row_pass(b, qw::ROW_LAST, r, s); });
@@ -666,8 +717,17 @@ int qw_batch_observables(qw_batch b, const void* psi, const qw_obs_spec* specs, 
     std::vector<double> all((size_t)kScalarsPerInst * b->n);
     if (e == hipSuccess)
         e = hipMemcpyAsync(all.data(), b->ws + b->lay.scalars, sizeof(double) * all.size(), hipMemcpyDeviceToHost, s);
+    qw::BatchSync sync{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&sync, dev_sync(b), sizeof sync, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bhip(b, e, "batched observables");
+    if (sync.failed.v) {
+        e = hipMemsetAsync(&dev_sync(b)->failed.v, 0, sizeof(unsigned), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bhip(b, e, "step loop status reset");
+        return bfail(b, QW_E_DEVICE,
+                     "a step-loop barrier wait ran past its limit: the launch ended early and psi is not valid");
+    }
     bool finite = true;
     for (int i = 0; i < b->n; ++i)
         for (int q = 0; q < per; ++q) {
@@ -715,6 +775,24 @@ int qw_batch_set_launch(qw_batch b, int32_t row_wg_per_cu, int32_t col_wg_per_cu
     return QW_OK;
 }
 
+int qw_batch_set_loop(qw_batch b, int32_t wg_per_cu, double wait_limit_s, int32_t* max_wg_per_cu)
+{
+    if (!b) return bfail(nullptr, QW_E_ARG, "batch is NULL");
+    if (!(wait_limit_s >= 0.0 && wait_limit_s <= 60.0)) return bfail(b, QW_E_ARG, "wait_limit_s must be in [0, 60]");
+    int coop = 0;
+    hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device);
+    if (e != hipSuccess) return bhip(b, e, "device attribute");
+    const int fit = b->p.loop_blocks_per_cu();
+    if (max_wg_per_cu) *max_wg_per_cu = coop ? fit : 0;
+    if (wg_per_cu == -1) return QW_OK;
+    if (wg_per_cu < 0) return bfail(b, QW_E_ARG, "wg_per_cu must be -1, 0 or positive");
+    if (wg_per_cu > 0 && !coop) return bfail(b, QW_E_DEVICE, "the device has no cooperative launches");
+    if (wg_per_cu > fit) return bfail(b, QW_E_ARG, "wg_per_cu = %d: at most %d step-loop workgroups fit one CU", wg_per_cu, fit);
+    b->loop_wg_per_cu = wg_per_cu;
+    b->spin_ticks = (unsigned long long)((wait_limit_s > 0.0 ? wait_limit_s : 2.0) * 1e3 * b->wall_khz);
+    return QW_OK;
+}
+
 int qw_batch_autotune(qw_batch b, const void* psi, double dt, int32_t reps, double* report, int32_t report_len,
                       int32_t* n_rows, void* hip_stream)
 {
@@ -723,9 +801,11 @@ int qw_batch_autotune(qw_batch b, const void* psi, double dt, int32_t reps, doub
     if (reps < 1 || reps > 10000) return bfail(b, QW_E_ARG, "reps must be in [1, 10000]");
     if (!qwh::finite_all({dt})) return bfail(b, QW_E_ARG, "dt must be finite");
     if (report_len > 0 && !report) return bfail(b, QW_E_ARG, "report is NULL");
+    // the middle-step candidates run (reps + 1) chunks of steps
+    const int chunk = b->graph_steps > 0 ? b->graph_steps : kDefaultGraphSteps;
     for (int i = 0; i < b->n; ++i) {
         std::string msg;
-        rc = qwh::check_phases(b->inst[i].grid, b->inst[i].beam, true, reps, 0.0, dt, &msg);
+        rc = qwh::check_phases(b->inst[i].grid, b->inst[i].beam, true, (int64_t)(reps + 1) * chunk + 1, 0.0, dt, &msg);
         if (rc != QW_OK) return bfail(b, rc, "instance %d: %s", i, msg.c_str());
     }
     hipStream_t s = as_stream(hip_stream);
@@ -830,6 +910,29 @@ int qw_batch_autotune(qw_batch b, const void* psi, double dt, int32_t reps, doub
     }
     b->row_wg_per_cu = e == hipSuccess ? best_rw : save_rw;
     b->col_wg_per_cu = e == hipSuccess ? best_cw : save_cw;
+    // middle steps with the chosen shapes: graph replays (0) against the step
+    // loop at every workgroup count per CU that fits, per step over chunks
+    const int save_loop = b->loop_wg_per_cu;
+    int best_loop = 0;
+    if (e == hipSuccess && rc == QW_OK) {
+        int coop = 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device) != hipSuccess) coop = 0;
+        const int fit = coop ? b->p.loop_blocks_per_cu() : 0;
+        double best = 1e30;
+        for (int w = 0; w <= fit && e == hipSuccess; ++w) {
+            b->loop_wg_per_cu = w;
+            e = qw::launch_clock_set(dev_time(b), 0.0, dt, 1, s);
+            if (e != hipSuccess) break;
+            const double us = time_it([&] { return run_middle(b, plane, 1, 1 + chunk, true, s); }) / chunk;
+            if (e != hipSuccess) break;
+            put(4, w, 0, us);
+            if (us < best) {
+                best = us;
+                best_loop = w;
+            }
+        }
+    }
+    b->loop_wg_per_cu = e == hipSuccess ? best_loop : save_loop;
     b->timing = was_timing;
     drop_graph(b);
     if (ev0) (void)hipEventDestroy(ev0);

@@ -7,13 +7,16 @@
 // RPW = TX = 256 / (2 N / E).  With E elements per lane a tile always covers
 // 128 E cells, so the items of all instances cost the same and a launch
 // balances itself.  The launch is persistent when asked: fewer workgroups
-// than items, each walking its own strided share of the list.
+// than items, each walking its own strided share of the list.  The step loop
+// kernel runs many middle steps in one cooperative launch, with grid-wide
+// barriers between the column and row phases.
 //
 // The transform of each length comes in schedule variants (the same E,
 // other radix orders); the hot modes (ROW_MID, COL_PROP) take the variant
 // the batch's autotuner picked per length, the others the default plan.
 #pragma once
 #include "qw_kernels.inl"
+#include "qw_batch_loop.hpp"
 
 #ifndef QW_WPE_BATCH_ROW
 #define QW_WPE_BATCH_ROW 2
@@ -215,6 +218,134 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(Q
 }
 
 // ---------------------------------------------------------------------------
+// persistent step loop: `steps` middle steps (column pass, then middle row
+// pass) in one cooperative launch, a grid-wide barrier between the phases
+// ---------------------------------------------------------------------------
+#ifndef QW_WPE_BATCH_LOOP
+#define QW_WPE_BATCH_LOOP 2
+#endif
+
+__device__ __forceinline__ unsigned sync_load(unsigned* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// thread 0: wait until *p >= want; false once the wait runs past spin_ticks
+// or another workgroup has recorded a failure (then records one itself)
+__device__ __forceinline__ bool sync_wait(unsigned* p, unsigned want, BatchSync* s, unsigned long long spin_ticks)
+{
+    const unsigned long long start = (unsigned long long)wall_clock64();
+    while (sync_load(p) < want) {
+        if (sync_load(&s->failed.v) != 0u || (unsigned long long)wall_clock64() - start > spin_ticks) {
+            __hip_atomic_store(&s->failed.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+// Grid-wide barrier number k (1, 2, ...).  The launch is cooperative, so
+// every workgroup is resident.  Arrivals are counted per group of
+// gridDim.x / 8 workgroups; the last arrival of a group counts the group in
+// globally, waits for all 8 and then lets its group pass, so each polled
+// word has at most one group's workgroups on it (one counter polled by
+// every workgroup, with every wave writing back L2, cost 135 against 46 us
+// per step of eight 256^2 instances).  Ordering, all at agent scope: a
+// workgroup's stores are complete (every wave waits for its own) before
+// thread 0 arrives with a release; the group's last arrival acquires them
+// with that same read-modify-write and releases them with its global
+// arrival; the last group's release is acquired by each group's last
+// arrival before it releases its group, and each workgroup acquires after
+// its wait, so the next phase sees what the previous one wrote from every
+// XCD.  Every wait is bounded by
+// spin_ticks of the constant-rate wall clock: past it, or once another
+// workgroup has recorded a failure, the workgroup records the failure
+// (sticky, read by the host) and the loop ends.
+__device__ __forceinline__ bool loop_barrier(BatchSync* s, unsigned k, unsigned long long spin_ticks, int* flag)
+{
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = blockIdx.x & 7u, per = gridDim.x >> 3;
+        const unsigned n = __hip_atomic_fetch_add(&s->group_arrived[g].v, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (n == k * per) {
+            __hip_atomic_fetch_add(&s->arrived.v, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            ok = sync_wait(&s->arrived.v, 8u * k, s, spin_ticks);
+            if (ok) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&s->group_pass[g].v, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            ok = sync_wait(&s->group_pass[g].v, k, s, spin_ticks);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the CU's L1 and the XCD's L2 drop stale lines
+        *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// Every workgroup leaves through here; the last one to leave zeroes the
+// counters for the next launch on the stream.  A workgroup counts itself out
+// only after its last wait, so no wait can see the reset.
+__device__ __forceinline__ void loop_depart(BatchSync* s)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned d = __hip_atomic_fetch_add(&s->departed.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (d + 1 == gridDim.x) {
+            __hip_atomic_store(&s->arrived.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int g = 0; g < 8; ++g) {
+                __hip_atomic_store(&s->group_arrived[g].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&s->group_pass[g].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __hip_atomic_store(&s->departed.v, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Middle steps j0 .. j0 + steps - 1 (rows.j = j0, absolute step indices):
+// per step every workgroup walks its share of the column items, meets the
+// others at the barrier, walks its share of the row items, and meets them
+// again before the next step.  The items, their order within a phase and
+// the tile bodies are those of the one-launch-per-pass kernels, so the
+// results are the same bit for bit.
+template <typename T>
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(QW_WPE_BATCH_LOOP))) void batch_loop(
+    BatchLaunch cols, BatchLaunch rows, int steps, BatchSync* sync, unsigned long long spin_ticks)
+{
+    constexpr int LG = batch_family<T>::lg_max;
+    __shared__ cx<T> lds[cmax(batch_lds_row<T, LG>(), batch_lds_col<T, LG>())];
+    __shared__ int flag;
+    const item_range cr = batch_items(cols.n_items), rr = batch_items(rows.n_items);
+    const int j0 = rows.j;
+    unsigned k = 0;
+    for (int s = 0; s < steps; ++s) {
+        for (int it = cr.it; it < cr.end; it += cr.step) {
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            batch_col_item<T, COL_PROP>(cols, it, lds, tid);
+            __syncthreads();
+        }
+        if (!loop_barrier(sync, ++k, spin_ticks, &flag)) break;
+        BatchLaunch r = rows;
+        r.j = j0 + s;
+        for (int it = rr.it; it < rr.end; it += rr.step) {
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            batch_row_item<T, ROW_MID>(r, it, lds, tid);
+            __syncthreads();
+        }
+        if (s + 1 == steps) break;
+        if (!loop_barrier(sync, ++k, spin_ticks, &flag)) break;
+    }
+    loop_depart(sync);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -294,6 +425,26 @@ hipError_t launch_batch_col(int mode, int grid, bool persist, const BatchLaunch&
     return hipGetLastError();
 }
 
+// workgroups of the step loop that fit one CU (0 if the query fails)
+template <typename T>
+int batch_loop_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_loop<T>, kBatchThreads, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+// one cooperative launch: the runtime refuses a grid that cannot be resident at once
+template <typename T>
+hipError_t launch_batch_loop(int grid, const BatchLaunch& cols, const BatchLaunch& rows, int steps, BatchSync* sync,
+                             unsigned long long spin_ticks, hipStream_t st)
+{
+    BatchLaunch c = cols, r = rows;
+    void* args[] = {&c, &r, &steps, &sync, &spin_ticks};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&batch_loop<T>), dim3(grid), dim3(kBatchThreads),
+                                      args, 0, st);
+}
+
 }  // namespace qw
 
 #define QW_DEFINE_BATCH_LAUNCHERS(T, SUF)                                                              \
@@ -313,5 +464,11 @@ hipError_t launch_batch_col(int mode, int grid, bool persist, const BatchLaunch&
     hipError_t launch_batch_col_##SUF(int mode, int grid, bool persist, const BatchLaunch& b, hipStream_t s) \
     {                                                                                                  \
         return launch_batch_col<T>(mode, grid, persist, b, s);                                         \
+    }                                                                                                  \
+    int batch_loop_blocks_per_cu_##SUF() { return batch_loop_blocks_per_cu<T>(); }                     \
+    hipError_t launch_batch_loop_##SUF(int grid, const BatchLaunch& c, const BatchLaunch& r, int steps, \
+                                       BatchSync* sync, unsigned long long ticks, hipStream_t s)        \
+    {                                                                                                  \
+        return launch_batch_loop<T>(grid, c, r, steps, sync, ticks, s);                                \
     }                                                                                                  \
     }

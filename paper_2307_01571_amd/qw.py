@@ -39,7 +39,7 @@ EXPORTED = ("qw_workspace_bytes", "qw_init_grid", "qw_set_beam", "qw_set_frame",
             "qw_destroy",
             "qw_batch_layout", "qw_batch_init", "qw_batch_init_packets", "qw_batch_step_n",
             "qw_batch_observables", "qw_batch_schedule", "qw_batch_set_schedule", "qw_batch_set_launch",
-            "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
+            "qw_batch_set_loop", "qw_batch_autotune", "qw_batch_kernel_timing", "qw_batch_kernel_times", "qw_batch_last_error",
             "qw_batch_destroy",
             "qw_mlp_param_count", "qw_mlp_workspace_bytes", "qw_mlp_init", "qw_mlp_set_params",
             "qw_mlp_set_output_map", "qw_mlp_set_spread_weights", "qw_mlp_get_params", "qw_mlp_forward", "qw_mlp_predict", "qw_mlp_predict_static",
@@ -128,6 +128,7 @@ def lib():
     L.qw_batch_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32]
     L.qw_batch_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.qw_batch_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.qw_batch_set_loop.argtypes = [vp, ctypes.c_int32, ctypes.c_double, i32p]
     L.qw_batch_autotune.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int32, dp, ctypes.c_int32, i32p, vp]
     L.qw_batch_kernel_timing.argtypes = [vp, ctypes.c_int]
     L.qw_batch_kernel_times.argtypes = [vp, dp, ctypes.c_int32, vp]
@@ -318,6 +319,14 @@ def qw_batch_set_schedule(b: int, log2n: int, pass_: int, v: int) -> None:
 def qw_batch_set_launch(b: int, row_wg_per_cu: int, col_wg_per_cu: int, graph_steps: int) -> None:
     _bcheck(lib().qw_batch_set_launch(ctypes.c_void_p(b), int(row_wg_per_cu), int(col_wg_per_cu),
                                       int(graph_steps)), b)
+
+
+def qw_batch_set_loop(b: int, wg_per_cu: int, wait_limit_s: float = 0.0) -> int:
+    """Step loop on (wg_per_cu > 0) or off (0); -1 only queries.  Returns how
+    many step-loop workgroups fit one CU (0: no cooperative launches)."""
+    fit = ctypes.c_int32()
+    _bcheck(lib().qw_batch_set_loop(ctypes.c_void_p(b), int(wg_per_cu), float(wait_limit_s), ctypes.byref(fit)), b)
+    return int(fit.value)
 
 
 def qw_batch_autotune(b: int, psi_ptr: int, dt: float, reps: int, stream: int, max_rows: int = 256):
@@ -583,6 +592,9 @@ class Batch:
 
     def set_launch(self, row_wg_per_cu: int = 0, col_wg_per_cu: int = 0, graph_steps: int = 64) -> None:
         qw_batch_set_launch(self.b, row_wg_per_cu, col_wg_per_cu, graph_steps)
+
+    def set_loop(self, wg_per_cu: int, wait_limit_s: float = 0.0) -> int:
+        return qw_batch_set_loop(self.b, wg_per_cu, wait_limit_s)
 
     def autotune(self, dt: float, reps: int = 20):
         return qw_batch_autotune(self.b, self.psi.data_ptr(), dt, reps, self.stream())

@@ -166,6 +166,7 @@ def test_batch_calls_reject_null_handle():
     vp = ctypes.c_void_p
     assert L.qw_batch_step_n(None, vp(256), 1, 0.0, 1e-5, None) == qw.QW_E_ARG
     assert L.qw_batch_set_launch(None, 0, 0, 0) == qw.QW_E_ARG
+    assert L.qw_batch_set_loop(None, 0, 0.0, None) == qw.QW_E_ARG
     assert L.qw_batch_set_schedule(None, 6, 0, 0) == qw.QW_E_ARG
     assert L.qw_batch_kernel_timing(None, 1) == qw.QW_E_ARG
     L.qw_batch_destroy(None)

@@ -6,6 +6,11 @@
 * FP32 batches against the single-instance FP32 path, element by element:
   identical bits, with and without the captured step-loop graph and with
   persistent launches (the batched kernels run the same arithmetic);
+* the step loop (middle steps in cooperative launches with grid-wide
+  barriers between the phases): FP64 against the oracle as above, FP32
+  identical bits to the launch-per-pass path, and a barrier wait past its
+  limit (a zero limit set from the host; every workgroup still leaves the
+  launch normally) reported by the next observables call;
 * the autotuner leaves psi untouched and its choices keep FP64 parity;
 * the full batching workload (96 instances of 256^2 / 512^2 / 1024^2 FP32,
   2e4 steps, autotuned) against the GPU FP64 single-instance runs of sampled
@@ -69,13 +74,22 @@ def make_batch(cases, prec):
     return bt
 
 
-@pytest.mark.parametrize("graph_steps", [0, 8])
-def test_batch_f64_matches_oracle(graph_steps):
+def loop_capacity(bt):
+    """Step-loop workgroups that fit one CU (the device must allow cooperative launches)."""
+    fit = bt.set_loop(-1)
+    assert fit >= 1, "no step-loop workgroup fits a CU, or no cooperative launches"
+    return fit
+
+
+@pytest.mark.parametrize("graph_steps,loop", [(0, 0), (8, 0), (8, 2), (0, 1)])
+def test_batch_f64_matches_oracle(graph_steps, loop):
     cases = mixed_instances(MIXED)
     steps, t0, dt = 37, 0.25 * W.T_L, W.DT
-    print_case(test="batch_f64", graph_steps=graph_steps, steps=steps)
+    print_case(test="batch_f64", graph_steps=graph_steps, loop=loop, steps=steps)
     bt = make_batch(cases, F64)
     bt.set_launch(0, 0, graph_steps)
+    if loop:
+        bt.set_loop(min(loop, loop_capacity(bt)))
     bt.step(steps, t0, dt)
     obs = bt.observables([o for *_, o in cases])
     for i, (g, b, p, o) in enumerate(cases):
@@ -134,6 +148,58 @@ def test_batch_f32_is_bitwise_the_single_instance_path(launch):
     bt.close()
 
 
+@pytest.mark.parametrize("wg,graph_steps", [(1, 16), (2, 0), (2, 5)])
+def test_step_loop_is_bitwise_the_launch_per_pass_path(wg, graph_steps):
+    """FP32 uneven grids (64 to 2048 points per line): the middle steps in
+    step-loop launches of graph_steps steps (64 when 0) against the same
+    batch advanced one launch per pass: identical bits, and no barrier wait
+    ran past its limit (observables would raise)."""
+    sizes = [(256, 256, 8, 8), (512, 512, 16, 16), (1024, 1024, 32, 32), (64, 256, 2, 8), (2048, 64, 64, 2)]
+    cases = mixed_instances(sizes, seed=7, ramp=2.0)
+    steps = 41
+    print_case(test="step_loop_f32_bitwise", wg=wg, graph_steps=graph_steps, steps=steps)
+    ref = make_batch(cases, F32)
+    ref.set_launch(0, 0, 0)
+    ref.step(steps, 0.0, W.DT)
+    bt = make_batch(cases, F32)
+    bt.set_launch(0, 0, graph_steps)
+    bt.set_loop(min(wg, loop_capacity(bt)))
+    bt.step(steps, 0.0, W.DT)
+    bt.observables([o for *_, o in cases])
+    for i in range(len(cases)):
+        got, exp = bt.state(i), ref.state(i)
+        assert np.array_equal(got, exp), (i, float(np.max(np.abs(got - exp))))
+    bt.close()
+    ref.close()
+
+
+def test_step_loop_wait_limit_is_reported_once():
+    """A barrier wait limit of zero, set from the host, ends the step-loop
+    launch early (every workgroup leaves normally): the next observables
+    call reports it; the report clears it, and the loop with the default
+    limit then reproduces the launch-per-pass result bit for bit."""
+    cases = mixed_instances(MIXED[:3], seed=5)
+    specs = [o for *_, o in cases]
+    print_case(test="step_loop_wait_limit")
+    bt = make_batch(cases, F32)
+    bt.set_launch(0, 0, 0)
+    bt.set_loop(1, wait_limit_s=1e-12)
+    bt.step(10, 0.0, W.DT)
+    with pytest.raises(qw.QWError, match="step-loop barrier"):
+        bt.observables(specs)
+    bt.set_loop(1)
+    bt.init_packets([p for _, _, p, _ in cases])
+    bt.step(10, 0.0, W.DT)
+    bt.observables(specs)
+    ref = make_batch(cases, F32)
+    ref.set_launch(0, 0, 0)
+    ref.step(10, 0.0, W.DT)
+    for i in range(len(cases)):
+        assert np.array_equal(bt.state(i), ref.state(i)), i
+    bt.close()
+    ref.close()
+
+
 def test_batch_step_loop_captured_by_the_caller():
     # qw_batch_step_n inside the caller's own graph capture (torch.cuda.graph):
     # plain launches are recorded even where the batch would replay its own
@@ -187,7 +253,8 @@ def test_batch_autotune_leaves_psi_and_keeps_parity():
     torch.cuda.synchronize()
     assert torch.equal(before, bt.psi)
     kinds = {int(r[0]) for r in rows}
-    assert kinds == {0, 1, 2, 3}
+    assert kinds == {0, 1, 2, 3, 4}
+    assert {int(r[1]) for r in rows if int(r[0]) == 4} == set(range(loop_capacity(bt) + 1))
     assert all(r[3] > 0 for r in rows)
     steps = 20
     bt.step(steps, 0.0, W.DT)
@@ -204,6 +271,10 @@ def test_batch_errors_are_reported():
         bt.set_schedule(6, 0, 3)  # 64 has two FP64 variants
     with pytest.raises(qw.QWError):
         bt.set_launch(-1, 0, 0)
+    with pytest.raises(qw.QWError):
+        bt.set_loop(1, wait_limit_s=61.0)
+    with pytest.raises(qw.QWError):
+        bt.set_loop(bt.set_loop(-1) + 1)
     with pytest.raises(qw.QWError):
         bt.step(-1, 0.0, W.DT)
     o = W.ObsSpec(band_ref_idx=0, band_half_idx=4, window_idx=4)
