@@ -508,6 +508,9 @@ def main():
     ap.add_argument("--record-counters", metavar="DIR",
                     help="write the traffic record from rocprofv3 --pmc runs under DIR (fetch/, write/, sq/, "
                          "copy_fetch/, copy_write/) and exit; runs without a GPU")
+    ap.add_argument("--small-batch", action="store_true",
+                    help="only run the launch-bound batch (8 instances of 256^2 FP32) with graph replays and "
+                         "with the step loop, and print that comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
                          "128 MiB written), the reference for bandwidth and traffic counters")
@@ -535,6 +538,10 @@ def main():
     qw.lib()
     wl = W.large()
     cells = wl.grid.nx * wl.grid.ny
+
+    if a.small_batch:
+        print(json.dumps({"small_batch": loop_small(qw, W, torch)}), flush=True)
+        return
 
     if a.copy_probe:
         us, gbs, nbytes = copy_rate(torch, wl)
