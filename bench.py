@@ -246,7 +246,9 @@ def batch_section(qw, W, torch, steps, single_steps):
         cand = [(r[3], int(r[1])) for r in rows if int(r[0]) == kind]
         launches[pass_ + "_wg_per_cu"] = min(cand)[1] if cand else 0
     # middle steps: graph replays (0) against the step loop (k workgroups per CU)
-    middle = {("graph" if int(r[1]) == 0 else f"loop_{int(r[1])}"): round(r[3], 2) for r in rows if int(r[0]) == 4}
+    def loop_name(w):
+        return "graph" if w == 0 else ("instance" if w == qw.QW_LOOP_INSTANCE else f"loop_{w}")
+    middle = {loop_name(int(r[1])): round(r[3], 2) for r in rows if int(r[0]) == 4}
     cand = [(r[3], int(r[1])) for r in rows if int(r[0]) == 4]
     launches["loop_wg_per_cu"] = min(cand)[1] if cand else 0
     bt.init_packets([w.packet for w in wls])
@@ -289,29 +291,31 @@ def batch_section(qw, W, torch, steps, single_steps):
             "avg_launch_us": {"row": round(row_us, 2), "col": round(col_us, 2)},
             "middle_step_us_autotune": middle,
             "small_batch": loop_small(qw, W, torch),
+            "tiny_batch": loop_small(qw, W, torch, n_inst=512, n=64),
             "pass_GBps": {"row": round(64 * cells / (row_us * 1e-6) / 1e9, 1),
                           "col": round(64 * cells / (col_us * 1e-6) / 1e9, 1)},
             "schedules": chosen, "launch": launches}
 
 
 def loop_small(qw, W, torch, n_inst=8, n=256, steps=641):
-    """A launch-bound batch (8 instances of 256^2 FP32): microseconds per step
-    with graph replays and with the step loop at every workgroup count per CU
-    that fits, and whether the final states agree bit for bit."""
+    """A launch-bound batch (n_inst instances of n^2 FP32): microseconds per
+    step with graph replays, with the grid-wide step loop at every workgroup
+    count per CU that fits and with one workgroup per instance, and whether
+    the final states agree bit for bit."""
     import numpy as np
     cases = []
     for i in range(n_inst):
         g = W.square_box(n, n // 32)
-        cases.append((g, W.BeamSpec(a0=0.3 + 0.1 * i, w0=2.0 * W.LAMBDA_L, ramp_periods=0.0),
+        cases.append((g, W.BeamSpec(a0=0.3 + 0.1 * (i % 8), w0=2.0 * W.LAMBDA_L, ramp_periods=0.0),
                       W.PacketSpec(sigma_x=1.0)))
     out, ref = {}, None
     fit = 0
-    for loop in range(0, 3):
+    for loop in (0, 1, 2, qw.QW_LOOP_INSTANCE):
         bt = qw.Batch([(g, b) for g, b, _ in cases], qw.QW_F32)
         fit = bt.set_loop(-1)
         if loop > fit:
             bt.close()
-            break
+            continue
         bt.set_loop(loop)
         bt.init_packets([p for _, _, p in cases])
         bt.step(steps, 0.0, W.DT)
@@ -326,7 +330,8 @@ def loop_small(qw, W, torch, n_inst=8, n=256, steps=641):
         bt.close()
         same = None if ref is None else all(np.array_equal(a, b) for a, b in zip(st, ref))
         ref = st if ref is None else ref
-        out["graph" if loop == 0 else f"loop_{loop}"] = {"us_per_step": round(us, 2), "bitwise_equal": same}
+        name = "graph" if loop == 0 else ("instance" if loop == qw.QW_LOOP_INSTANCE else f"loop_{loop}")
+        out[name] = {"us_per_step": round(us, 2), "bitwise_equal": same}
     log(f"batch: small batch {n_inst}x{n}^2 {out}")
     return {"workload": f"{n_inst} instances of {n}^2 FP32, {steps} steps", "loop_fits_per_cu": fit, **out}
 
@@ -509,8 +514,8 @@ def main():
                     help="write the traffic record from rocprofv3 --pmc runs under DIR (fetch/, write/, sq/, "
                          "copy_fetch/, copy_write/) and exit; runs without a GPU")
     ap.add_argument("--small-batch", action="store_true",
-                    help="only run the launch-bound batch (8 instances of 256^2 FP32) with graph replays and "
-                         "with the step loop, and print that comparison")
+                    help="only run the launch-bound batches (8 instances of 256^2, 512 of 64^2, FP32) with "
+                         "graph replays and with the step loops, and print that comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only time torch's plain device copy of one 2048^2 FP32 state (128 MiB read + "
                          "128 MiB written), the reference for bandwidth and traffic counters")
@@ -540,7 +545,8 @@ def main():
     cells = wl.grid.nx * wl.grid.ny
 
     if a.small_batch:
-        print(json.dumps({"small_batch": loop_small(qw, W, torch)}), flush=True)
+        print(json.dumps({"small_batch": loop_small(qw, W, torch),
+                          "tiny_batch": loop_small(qw, W, torch, n_inst=512, n=64)}), flush=True)
         return
 
     if a.copy_probe:

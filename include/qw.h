@@ -292,18 +292,22 @@ int qw_batch_set_schedule(qw_batch b, int32_t log2n, int32_t pass, int32_t v);
  * step directly. */
 int qw_batch_set_launch(qw_batch b, int32_t row_wg_per_cu, int32_t col_wg_per_cu, int32_t graph_steps);
 
-/* Step loop (the batched form's persistent launch).  wg_per_cu = 0 (the
+/* Step loop (the batched form's persistent launches).  wg_per_cu = 0 (the
  * default) turns it off.  k > 0: qw_batch_step_n runs its middle steps in
  * cooperative launches of k workgroups per compute unit (at most the number
  * that fit one CU, *max_wg_per_cu when not NULL; the grid never exceeds the
  * work items), each advancing up to graph_steps steps: every workgroup
  * walks its share of the column tiles, all meet at a grid-wide barrier,
- * then the row tiles, and a barrier again.  The arithmetic and the results
- * are those of the one-launch-per-pass path, bit for bit.  wait_limit_s
- * (0: 2 s; at most 60) bounds each barrier wait; a wait past it ends the
- * launch early and leaves psi invalid, and the next qw_batch_observables
- * returns QW_E_DEVICE saying so.  Returns QW_E_DEVICE if the device has no
+ * then the row tiles, and a barrier again.  QW_LOOP_INSTANCE: launches of
+ * one workgroup per instance, each running its instance's column and row
+ * tiles for up to graph_steps steps with no grid-wide barrier (for batches
+ * of many small grids).  The arithmetic and the results are those of the
+ * one-launch-per-pass path, bit for bit.  wait_limit_s (0: 2 s; at most
+ * 60) bounds each barrier wait; a wait past it ends the launch early and
+ * leaves psi invalid, and the next qw_batch_observables returns QW_E_DEVICE
+ * saying so.  Returns QW_E_DEVICE for k > 0 if the device has no
  * cooperative launches.  wg_per_cu = -1 only reports *max_wg_per_cu. */
+#define QW_LOOP_INSTANCE (-2)
 int qw_batch_set_loop(qw_batch b, int32_t wg_per_cu, double wait_limit_s, int32_t *max_wg_per_cu);
 
 /* Autotuner: times, on a copy of psi in the workspace (psi is not
@@ -312,10 +316,11 @@ int qw_batch_set_loop(qw_batch b, int32_t wg_per_cu, double wait_limit_s, int32_
  * of each.  reps launches per candidate.  report (optional, report_len
  * doubles) receives rows of 4 values (kind, a, b, microseconds per launch):
  * kind 0 row schedule (a = log2n, b = variant), 1 column schedule,
- * 2 row launch (a = wg_per_cu), 3 column launch, 4 middle steps (a = step
- * loop workgroups per CU, 0 for the graph replays; microseconds per step,
- * graph_steps (64 when 0) steps per launch); *n_rows their count.  Kind 4
- * keeps the step loop only where it is faster.  Waits for hip_stream. */
+ * 2 row launch (a = wg_per_cu), 3 column launch, 4 middle steps (a = the
+ * step loop's wg_per_cu, 0 for the graph replays, QW_LOOP_INSTANCE;
+ * microseconds per step, graph_steps (64 when 0) steps per launch);
+ * *n_rows their count.  Kind 4 keeps the step loop only where it is
+ * faster.  Waits for hip_stream. */
 int qw_batch_autotune(qw_batch b, const void *psi, double dt, int32_t reps, double *report, int32_t report_len,
                       int32_t *n_rows, void *hip_stream);
 

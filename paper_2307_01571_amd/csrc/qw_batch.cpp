@@ -64,6 +64,12 @@ struct Prec {
         return f32 ? qw::launch_batch_loop_f32(grid, c, r, steps, sync, ticks, s)
                    : qw::launch_batch_loop_f64(grid, c, r, steps, sync, ticks, s);
     }
+    hipError_t inst_loop(int n, const qw::BatchLaunch& c, const qw::BatchLaunch& r, const qw::BatchInstItems* q,
+                         int steps, hipStream_t s) const
+    {
+        return f32 ? qw::launch_batch_inst_loop_f32(n, c, r, q, steps, s)
+                   : qw::launch_batch_inst_loop_f64(n, c, r, q, steps, s);
+    }
     hipError_t beam(void* bx, void* by, const qw::BeamArgs& a, hipStream_t s) const
     {
         return f32 ? qw::launch_beam_tables_f32(bx, by, a, s) : qw::launch_beam_tables_f64(bx, by, a, s);
@@ -97,13 +103,14 @@ int n_variants(const Prec& p, int lg)
 struct BatchLayout {
     std::vector<int64_t> state_off;
     size_t state_bytes = 0;
-    size_t time = 0, sync = 0, desc = 0, row_items = 0, col_items = 0, scalars = 0, rownorm = 0, partial = 0, plane = 0;
+    size_t time = 0, sync = 0, inst_items = 0, desc = 0, row_items = 0, col_items = 0, scalars = 0, rownorm = 0, partial = 0, plane = 0;
     std::map<std::pair<int, int>, size_t> tw;             // (lg, variant) -> twiddle table
     std::vector<size_t> bx, by;                           // per instance field tables
     std::map<std::tuple<int, int, double, double, double>, size_t> ktab;  // (nx, ny, lx, ly, c) -> table
     std::vector<size_t> ktab_of;                          // per instance
     std::vector<int> row_base, col_tile_base;             // per instance: first row / first column tile
     std::vector<uint32_t> row_items_h, col_items_h;       // (instance << 16) | tile, grouped by length
+    std::vector<qw::BatchInstItems> inst_items_h;         // per instance: its ranges in the two lists
     std::map<int, std::pair<int, int>> row_range, col_range;  // lg -> [first, end) in the lists
     int n_rows = 0, n_col_tiles = 0;
     size_t total = 0;
@@ -172,18 +179,23 @@ int make_batch_layout(const qw_instance* inst, int n, BatchLayout* L, std::strin
     }
     L->n_rows = rb;
     L->n_col_tiles = cb;
+    L->inst_items_h.assign(n, qw::BatchInstItems{});
     for (int i : by_len(true)) {
         const int lg = ilog2(inst[i].grid.nx), rpw = p.lines_per_tile(lg);
         auto it = L->row_range.find(lg);
         if (it == L->row_range.end()) L->row_range[lg] = {(int)L->row_items_h.size(), 0};
+        L->inst_items_h[i].row_first = (int)L->row_items_h.size();
         for (int t = 0; t < (inst[i].grid.ny + rpw - 1) / rpw; ++t) L->row_items_h.push_back(((uint32_t)i << 16) | t);
+        L->inst_items_h[i].row_end = (int)L->row_items_h.size();
         L->row_range[lg].second = (int)L->row_items_h.size();
     }
     for (int i : by_len(false)) {
         const int lg = ilog2(inst[i].grid.ny), tx = p.lines_per_tile(lg);
         auto it = L->col_range.find(lg);
         if (it == L->col_range.end()) L->col_range[lg] = {(int)L->col_items_h.size(), 0};
+        L->inst_items_h[i].col_first = (int)L->col_items_h.size();
         for (int t = 0; t < (inst[i].grid.nx + tx - 1) / tx; ++t) L->col_items_h.push_back(((uint32_t)i << 16) | t);
+        L->inst_items_h[i].col_end = (int)L->col_items_h.size();
         L->col_range[lg].second = (int)L->col_items_h.size();
     }
     // workspace
@@ -195,6 +207,7 @@ int make_batch_layout(const qw_instance* inst, int n, BatchLayout* L, std::strin
     };
     L->time = take(sizeof(qw::StepClock));
     L->sync = take(sizeof(qw::BatchSync));
+    L->inst_items = take(sizeof(qw::BatchInstItems) * (size_t)n);
     L->desc = take(sizeof(qw::BatchInst) * (size_t)n);
     L->row_items = take(sizeof(uint32_t) * L->row_items_h.size());
     L->col_items = take(sizeof(uint32_t) * L->col_items_h.size());
@@ -246,7 +259,9 @@ struct qw_batch_s {
     int row_var[kMaxLg + 1] = {};
     int col_var[kMaxLg + 1] = {};
     int row_wg_per_cu = 0, col_wg_per_cu = 0, graph_steps = kDefaultGraphSteps;
-    // step loop: workgroups per CU (0: off) and the bound of a barrier wait in wall-clock ticks
+    // step loop: 0 off, k > 0 grid-wide loop with k workgroups per CU,
+    // QW_LOOP_INSTANCE one workgroup per instance; the bound of a barrier
+    // wait in wall-clock ticks
     int loop_wg_per_cu = 0;
     double wall_khz = 1e5;
     unsigned long long spin_ticks = 200000000ull;
@@ -477,6 +492,9 @@ hipError_t loop_launch(qw_batch b, char* psi, int64_t k, int count, hipStream_t 
     r.j = (int)k;
     r.use_counter = 0;
     r.tau_frac = 1.0;
+    if (b->loop_wg_per_cu == QW_LOOP_INSTANCE)
+        return b->p.inst_loop(b->n, c, r, reinterpret_cast<const qw::BatchInstItems*>(b->ws + b->lay.inst_items),
+                              count, s);
     const int items = std::max(c.n_items, r.n_items);
     const int grid = std::max(8, std::min(b->loop_wg_per_cu * b->n_cu, (items + 7) / 8 * 8) / 8 * 8);
     return b->p.loop(grid, c, r, count, dev_sync(b), b->spin_ticks, s);
@@ -489,7 +507,7 @@ hipError_t loop_launch(qw_batch b, char* psi, int64_t k, int count, hipStream_t 
 hipError_t run_middle(qw_batch b, char* psi, int64_t k, int64_t end, bool fast, hipStream_t s)
 {
     hipError_t e = hipSuccess;
-    if (fast && b->loop_wg_per_cu > 0) {
+    if (fast && b->loop_wg_per_cu != 0) {
         const int chunk = b->graph_steps > 0 ? b->graph_steps : kDefaultGraphSteps;
         for (; k < end && e == hipSuccess; k += chunk) e = loop_launch(b, psi, k, (int)std::min<int64_t>(chunk, end - k), s);
         return e;
@@ -602,6 +620,9 @@ int qw_batch_init(qw_batch* out, const qw_instance* inst, int32_t n, void* works
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ws + Y.col_items, Y.col_items_h.data(), sizeof(uint32_t) * Y.col_items_h.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + Y.inst_items, Y.inst_items_h.data(), sizeof(qw::BatchInstItems) * n,
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = qw::launch_clock_set(dev_time(b), 0.0, 0.0, 0, s);
     if (e == hipSuccess) e = hipMemsetAsync(dev_sync(b), 0, sizeof(qw::BatchSync), s);
@@ -785,7 +806,11 @@ int qw_batch_set_loop(qw_batch b, int32_t wg_per_cu, double wait_limit_s, int32_
     const int fit = b->p.loop_blocks_per_cu();
     if (max_wg_per_cu) *max_wg_per_cu = coop ? fit : 0;
     if (wg_per_cu == -1) return QW_OK;
-    if (wg_per_cu < 0) return bfail(b, QW_E_ARG, "wg_per_cu must be -1, 0 or positive");
+    if (wg_per_cu == QW_LOOP_INSTANCE) {
+        b->loop_wg_per_cu = wg_per_cu;
+        return QW_OK;
+    }
+    if (wg_per_cu < 0) return bfail(b, QW_E_ARG, "wg_per_cu must be -1, QW_LOOP_INSTANCE, 0 or positive");
     if (wg_per_cu > 0 && !coop) return bfail(b, QW_E_DEVICE, "the device has no cooperative launches");
     if (wg_per_cu > fit) return bfail(b, QW_E_ARG, "wg_per_cu = %d: at most %d step-loop workgroups fit one CU", wg_per_cu, fit);
     b->loop_wg_per_cu = wg_per_cu;
@@ -918,8 +943,12 @@ int qw_batch_autotune(qw_batch b, const void* psi, double dt, int32_t reps, doub
         int coop = 0;
         if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, b->device) != hipSuccess) coop = 0;
         const int fit = coop ? b->p.loop_blocks_per_cu() : 0;
+        std::vector<int> cand;
+        for (int w = 0; w <= fit; ++w) cand.push_back(w);
+        cand.push_back(QW_LOOP_INSTANCE);
         double best = 1e30;
-        for (int w = 0; w <= fit && e == hipSuccess; ++w) {
+        for (int w : cand) {
+            if (e != hipSuccess) break;
             b->loop_wg_per_cu = w;
             e = qw::launch_clock_set(dev_time(b), 0.0, dt, 1, s);
             if (e != hipSuccess) break;

@@ -345,6 +345,39 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(Q
     loop_depart(sync);
 }
 
+// One workgroup per instance: middle steps j0 .. j0 + steps - 1 of instance
+// blockIdx.x, its column items, then its row items, per step.  An
+// instance's data dependences stay inside its workgroup, so the barrier
+// after each item (workgroup-scope release and acquire) is the only one and
+// the launch needs no co-residency; the items, their order and the tile
+// bodies are those of the per-pass kernels, so the results are the same bit
+// for bit.  ranges[i] = (first row item, end, first column item, end).
+template <typename T>
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(QW_WPE_BATCH_LOOP))) void batch_inst_loop(
+    BatchLaunch cols, BatchLaunch rows, const BatchInstItems* ranges, int steps)
+{
+    constexpr int LG = batch_family<T>::lg_max;
+    __shared__ cx<T> lds[cmax(batch_lds_row<T, LG>(), batch_lds_col<T, LG>())];
+    const BatchInstItems q = ranges[blockIdx.x];
+    const int j0 = rows.j;
+    for (int s = 0; s < steps; ++s) {
+        for (int it = q.col_first; it < q.col_end; ++it) {
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            batch_col_item<T, COL_PROP>(cols, it, lds, tid);
+            __syncthreads();
+        }
+        BatchLaunch r = rows;
+        r.j = j0 + s;
+        for (int it = q.row_first; it < q.row_end; ++it) {
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            batch_row_item<T, ROW_MID>(r, it, lds, tid);
+            __syncthreads();
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -434,6 +467,14 @@ int batch_loop_blocks_per_cu()
     return nb;
 }
 
+template <typename T>
+hipError_t launch_batch_inst_loop(int n_inst, const BatchLaunch& cols, const BatchLaunch& rows,
+                                  const BatchInstItems* ranges, int steps, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_inst_loop<T>), dim3(n_inst), dim3(kBatchThreads), 0, st, cols, rows, ranges, steps);
+    return hipGetLastError();
+}
+
 // one cooperative launch: the runtime refuses a grid that cannot be resident at once
 template <typename T>
 hipError_t launch_batch_loop(int grid, const BatchLaunch& cols, const BatchLaunch& rows, int steps, BatchSync* sync,
@@ -470,5 +511,10 @@ hipError_t launch_batch_loop(int grid, const BatchLaunch& cols, const BatchLaunc
                                        BatchSync* sync, unsigned long long ticks, hipStream_t s)        \
     {                                                                                                  \
         return launch_batch_loop<T>(grid, c, r, steps, sync, ticks, s);                                \
+    }                                                                                                  \
+    hipError_t launch_batch_inst_loop_##SUF(int n, const BatchLaunch& c, const BatchLaunch& r,          \
+                                            const BatchInstItems* q, int steps, hipStream_t s)         \
+    {                                                                                                  \
+        return launch_batch_inst_loop<T>(n, c, r, q, steps, s);                                        \
     }                                                                                                  \
     }

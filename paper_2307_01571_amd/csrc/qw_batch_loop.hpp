@@ -22,13 +22,22 @@ struct BatchSync {
     BatchSyncSlot group_pass[8];     // barrier index each group may pass
 };
 
+// an instance's work items: rows [row_first, row_end) of the row list,
+// columns [col_first, col_end) of the column list
+struct BatchInstItems {
+    int row_first, row_end, col_first, col_end;
+};
+
 // step-loop workgroups that fit one CU (0 if the query fails); one
 // cooperative launch of grid workgroups running `steps` middle steps from
-// rows.j, each wait bounded by spin_ticks of the wall clock
+// rows.j, each wait bounded by spin_ticks of the wall clock; or one launch
+// of one workgroup per instance (n of them) running its own steps
 #define QW_DECLARE_LOOP_LAUNCHERS(SUF)                                                                    \
     int batch_loop_blocks_per_cu_##SUF();                                                                 \
     hipError_t launch_batch_loop_##SUF(int grid, const BatchLaunch& cols, const BatchLaunch& rows, int steps, \
-                                       BatchSync* sync, unsigned long long spin_ticks, hipStream_t s);
+                                       BatchSync* sync, unsigned long long spin_ticks, hipStream_t s);     \
+    hipError_t launch_batch_inst_loop_##SUF(int n, const BatchLaunch& cols, const BatchLaunch& rows,        \
+                                            const BatchInstItems* ranges, int steps, hipStream_t s);
 QW_DECLARE_LOOP_LAUNCHERS(f32)
 QW_DECLARE_LOOP_LAUNCHERS(f64)
 #undef QW_DECLARE_LOOP_LAUNCHERS

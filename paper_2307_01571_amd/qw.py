@@ -29,6 +29,8 @@ QW_F64 = 0
 QW_F32 = 1
 QW_MLP_STATIC_MAX_BATCH = 256  # qw_mlp.h
 
+QW_LOOP_INSTANCE = -2  # qw_batch_set_loop: one workgroup per instance
+
 QW_BEAM_NONE = 0
 QW_BEAM_STANDING_PARAXIAL = 1
 QW_BEAM_UNIFORM = 2
@@ -322,8 +324,9 @@ def qw_batch_set_launch(b: int, row_wg_per_cu: int, col_wg_per_cu: int, graph_st
 
 
 def qw_batch_set_loop(b: int, wg_per_cu: int, wait_limit_s: float = 0.0) -> int:
-    """Step loop on (wg_per_cu > 0) or off (0); -1 only queries.  Returns how
-    many step-loop workgroups fit one CU (0: no cooperative launches)."""
+    """Step loop on (wg_per_cu > 0: grid-wide barriers; QW_LOOP_INSTANCE: one
+    workgroup per instance) or off (0); -1 only queries.  Returns how many
+    grid-wide step-loop workgroups fit one CU (0: no cooperative launches)."""
     fit = ctypes.c_int32()
     _bcheck(lib().qw_batch_set_loop(ctypes.c_void_p(b), int(wg_per_cu), float(wait_limit_s), ctypes.byref(fit)), b)
     return int(fit.value)

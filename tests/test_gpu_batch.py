@@ -81,7 +81,7 @@ def loop_capacity(bt):
     return fit
 
 
-@pytest.mark.parametrize("graph_steps,loop", [(0, 0), (8, 0), (8, 2), (0, 1)])
+@pytest.mark.parametrize("graph_steps,loop", [(0, 0), (8, 0), (8, 2), (0, 1), (8, qw.QW_LOOP_INSTANCE)])
 def test_batch_f64_matches_oracle(graph_steps, loop):
     cases = mixed_instances(MIXED)
     steps, t0, dt = 37, 0.25 * W.T_L, W.DT
@@ -89,7 +89,7 @@ def test_batch_f64_matches_oracle(graph_steps, loop):
     bt = make_batch(cases, F64)
     bt.set_launch(0, 0, graph_steps)
     if loop:
-        bt.set_loop(min(loop, loop_capacity(bt)))
+        bt.set_loop(loop if loop == qw.QW_LOOP_INSTANCE else min(loop, loop_capacity(bt)))
     bt.step(steps, t0, dt)
     obs = bt.observables([o for *_, o in cases])
     for i, (g, b, p, o) in enumerate(cases):
@@ -148,12 +148,14 @@ def test_batch_f32_is_bitwise_the_single_instance_path(launch):
     bt.close()
 
 
-@pytest.mark.parametrize("wg,graph_steps", [(1, 16), (2, 0), (2, 5)])
+@pytest.mark.parametrize("wg,graph_steps", [(1, 16), (2, 0), (2, 5), (qw.QW_LOOP_INSTANCE, 16),
+                                             (qw.QW_LOOP_INSTANCE, 0)])
 def test_step_loop_is_bitwise_the_launch_per_pass_path(wg, graph_steps):
     """FP32 uneven grids (64 to 2048 points per line): the middle steps in
-    step-loop launches of graph_steps steps (64 when 0) against the same
-    batch advanced one launch per pass: identical bits, and no barrier wait
-    ran past its limit (observables would raise)."""
+    step-loop launches of graph_steps steps (64 when 0), with grid-wide
+    barriers or one workgroup per instance, against the same batch advanced
+    one launch per pass: identical bits, and no barrier wait ran past its
+    limit (observables would raise)."""
     sizes = [(256, 256, 8, 8), (512, 512, 16, 16), (1024, 1024, 32, 32), (64, 256, 2, 8), (2048, 64, 64, 2)]
     cases = mixed_instances(sizes, seed=7, ramp=2.0)
     steps = 41
@@ -163,7 +165,7 @@ def test_step_loop_is_bitwise_the_launch_per_pass_path(wg, graph_steps):
     ref.step(steps, 0.0, W.DT)
     bt = make_batch(cases, F32)
     bt.set_launch(0, 0, graph_steps)
-    bt.set_loop(min(wg, loop_capacity(bt)))
+    bt.set_loop(wg if wg == qw.QW_LOOP_INSTANCE else min(wg, loop_capacity(bt)))
     bt.step(steps, 0.0, W.DT)
     bt.observables([o for *_, o in cases])
     for i in range(len(cases)):
@@ -254,7 +256,7 @@ def test_batch_autotune_leaves_psi_and_keeps_parity():
     assert torch.equal(before, bt.psi)
     kinds = {int(r[0]) for r in rows}
     assert kinds == {0, 1, 2, 3, 4}
-    assert {int(r[1]) for r in rows if int(r[0]) == 4} == set(range(loop_capacity(bt) + 1))
+    assert {int(r[1]) for r in rows if int(r[0]) == 4} == set(range(loop_capacity(bt) + 1)) | {qw.QW_LOOP_INSTANCE}
     assert all(r[3] > 0 for r in rows)
     steps = 20
     bt.step(steps, 0.0, W.DT)
