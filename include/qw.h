@@ -320,7 +320,9 @@ int qw_batch_set_loop(qw_batch b, int32_t wg_per_cu, double wait_limit_s, int32_
  * step loop's wg_per_cu, 0 for the graph replays, QW_LOOP_INSTANCE;
  * microseconds per step, graph_steps (64 when 0) steps per launch);
  * *n_rows their count.  Kind 4 keeps the step loop only where it is
- * faster.  Waits for hip_stream. */
+ * faster; QW_LOOP_INSTANCE is a candidate only when no instance has more
+ * than 16 tiles per step (row and column tiles; 16 for 128^2 FP32).
+ * Waits for hip_stream. */
 int qw_batch_autotune(qw_batch b, const void *psi, double dt, int32_t reps, double *report, int32_t report_len,
                       int32_t *n_rows, void *hip_stream);
 

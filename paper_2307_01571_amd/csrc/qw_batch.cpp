@@ -30,6 +30,9 @@ constexpr int kScalarsPerInst = 128;  // [0] packet norm, [8 .. 8 + 3B + 3) obse
 constexpr int kMaxInstances = 65535;
 constexpr int kDefaultGraphSteps = 64;
 constexpr int kMaxLg = 12;
+// the autotuner times the instance loop only for batches whose instances
+// have at most this many tiles per step (a 128^2 FP32 instance has 16)
+constexpr int kInstLoopTiles = 16;
 
 struct Prec {
     bool f32;
@@ -945,7 +948,12 @@ int qw_batch_autotune(qw_batch b, const void* psi, double dt, int32_t reps, doub
         const int fit = coop ? b->p.loop_blocks_per_cu() : 0;
         std::vector<int> cand;
         for (int w = 0; w <= fit; ++w) cand.push_back(w);
-        cand.push_back(QW_LOOP_INSTANCE);
+        // one workgroup per instance walks the instance's tiles one after
+        // another: timed only where no instance has more than kInstLoopTiles
+        int most = 0;
+        for (const auto& q : b->lay.inst_items_h)
+            most = std::max(most, q.row_end - q.row_first + q.col_end - q.col_first);
+        if (most <= kInstLoopTiles) cand.push_back(QW_LOOP_INSTANCE);
         double best = 1e30;
         for (int w : cand) {
             if (e != hipSuccess) break;

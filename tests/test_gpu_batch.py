@@ -256,7 +256,8 @@ def test_batch_autotune_leaves_psi_and_keeps_parity():
     assert torch.equal(before, bt.psi)
     kinds = {int(r[0]) for r in rows}
     assert kinds == {0, 1, 2, 3, 4}
-    assert {int(r[1]) for r in rows if int(r[0]) == 4} == set(range(loop_capacity(bt) + 1)) | {qw.QW_LOOP_INSTANCE}
+    # MIXED holds a 256^2 instance (64 tiles per step): no instance-loop candidate
+    assert {int(r[1]) for r in rows if int(r[0]) == 4} == set(range(loop_capacity(bt) + 1))
     assert all(r[3] > 0 for r in rows)
     steps = 20
     bt.step(steps, 0.0, W.DT)
@@ -264,6 +265,30 @@ def test_batch_autotune_leaves_psi_and_keeps_parity():
         ref, _ = oracle_run(g, b, p, o, steps, 0.0, W.DT)
         assert rel_l2(bt.state(i), ref) <= 1e-10
     bt.close()
+
+
+def test_autotune_times_the_instance_loop_on_small_grids():
+    """Six 64^2 FP32 instances (4 tiles per step each): the instance loop is
+    a middle-step candidate; on the default schedules, whichever middle-step
+    path the autotuner keeps advances the batch to the same bits as the
+    launch-per-pass path."""
+    cases = mixed_instances([(64, 64, 8, 8)] * 6, seed=19)
+    print_case(test="autotune_instance_loop")
+    bt = make_batch(cases, F32)
+    rows = bt.autotune(W.DT, reps=2)
+    assert qw.QW_LOOP_INSTANCE in {int(r[1]) for r in rows if int(r[0]) == 4}
+    for pass_ in (0, 1):  # default schedules (the tuned ones round differently); the loop choice stays
+        bt.set_schedule(6, pass_, 0)
+    bt.init_packets([p for _, _, p, _ in cases])
+    bt.step(70, 0.0, W.DT)
+    bt.observables([o for *_, o in cases])
+    ref = make_batch(cases, F32)
+    ref.set_launch(0, 0, 0)
+    ref.step(70, 0.0, W.DT)
+    for i in range(len(cases)):
+        assert np.array_equal(bt.state(i), ref.state(i)), i
+    bt.close()
+    ref.close()
 
 
 def test_batch_errors_are_reported():
