@@ -512,7 +512,8 @@ hipError_t run_middle(qw_batch b, char* psi, int64_t k, int64_t end, bool fast, 
     hipError_t e = hipSuccess;
     if (fast && b->loop_wg_per_cu != 0) {
         const int chunk = b->graph_steps > 0 ? b->graph_steps : kDefaultGraphSteps;
-        for (; k < end && e == hipSuccess; k += chunk) e = loop_launch(b, psi, k, (int)std::min<int64_t>(chunk, end - k), s);
+        for (; k < end && e == hipSuccess; k += chunk)
+            e = loop_launch(b, psi, k, (int)std::min<int64_t>(chunk, end - k), s);
         return e;
     }
     if (fast && b->graph_steps > 0 && end - k >= b->graph_steps) {
@@ -815,7 +816,8 @@ int qw_batch_set_loop(qw_batch b, int32_t wg_per_cu, double wait_limit_s, int32_
     }
     if (wg_per_cu < 0) return bfail(b, QW_E_ARG, "wg_per_cu must be -1, QW_LOOP_INSTANCE, 0 or positive");
     if (wg_per_cu > 0 && !coop) return bfail(b, QW_E_DEVICE, "the device has no cooperative launches");
-    if (wg_per_cu > fit) return bfail(b, QW_E_ARG, "wg_per_cu = %d: at most %d step-loop workgroups fit one CU", wg_per_cu, fit);
+    if (wg_per_cu > fit)
+        return bfail(b, QW_E_ARG, "wg_per_cu = %d: at most %d step-loop workgroups fit one CU", wg_per_cu, fit);
     b->loop_wg_per_cu = wg_per_cu;
     b->spin_ticks = (unsigned long long)((wait_limit_s > 0.0 ? wait_limit_s : 2.0) * 1e3 * b->wall_khz);
     return QW_OK;

@@ -353,8 +353,8 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(Q
 // bodies are those of the per-pass kernels, so the results are the same bit
 // for bit.  ranges[i] = (first row item, end, first column item, end).
 template <typename T>
-__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(QW_WPE_BATCH_LOOP))) void batch_inst_loop(
-    BatchLaunch cols, BatchLaunch rows, const BatchInstItems* ranges, int steps)
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(QW_WPE_BATCH_LOOP))) void
+batch_inst_loop(BatchLaunch cols, BatchLaunch rows, const BatchInstItems* ranges, int steps)
 {
     constexpr int LG = batch_family<T>::lg_max;
     __shared__ cx<T> lds[cmax(batch_lds_row<T, LG>(), batch_lds_col<T, LG>())];
