@@ -197,7 +197,19 @@ int make_batch_layout(const qw_instance* inst, int n, BatchLayout* L, std::strin
         auto it = L->col_range.find(lg);
         if (it == L->col_range.end()) L->col_range[lg] = {(int)L->col_items_h.size(), 0};
         L->inst_items_h[i].col_first = (int)L->col_items_h.size();
-        for (int t = 0; t < (inst[i].grid.nx + tx - 1) / tx; ++t) L->col_items_h.push_back(((uint32_t)i << 16) | t);
+        // Column tiles in groups that share 128-byte lines of a row (a cell
+        // is 4 complex values), the groups taken alternately from the left
+        // and the right: consecutive items run on one XCD at nearly the same
+        // time, and columns x and nx - x read the same rows of the kinetic
+        // table (indexed by |kx|), which then come from that XCD's L2.
+        const int T = (inst[i].grid.nx + tx - 1) / tx;
+        const int per_line = std::max(1, (int)(128 / (4 * p.cs)) / tx);
+        const int J = (T + per_line - 1) / per_line;
+        for (int q = 0; q < J; ++q) {
+            const int j = (q & 1) ? J - 1 - (q >> 1) : (q >> 1);
+            for (int u = 0; u < per_line && j * per_line + u < T; ++u)
+                L->col_items_h.push_back(((uint32_t)i << 16) | (uint32_t)(j * per_line + u));
+        }
         L->inst_items_h[i].col_end = (int)L->col_items_h.size();
         L->col_range[lg].second = (int)L->col_items_h.size();
     }
