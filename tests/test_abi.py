@@ -32,6 +32,26 @@ def test_header_declares_the_boundary():
     assert set(names) == set(qw.EXPORTED)
 
 
+def declared_constants():
+    """Integer constants of the headers: enum members and #defines of a plain number."""
+    out = {}
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        for m in re.finditer(r"\b(QW_[A-Z0-9_]+)\s*=\s*(-?\d+)\b", text):
+            out[m.group(1)] = int(m.group(2))
+        for m in re.finditer(r"^#define\s+(QW_[A-Z0-9_]+)\s+\(?(-?\d+)\)?\s*$", text, flags=re.M):
+            out[m.group(1)] = int(m.group(2))
+    return out
+
+
+def test_binding_constants_match_the_headers():
+    consts = declared_constants()
+    for must in ("QW_OK", "QW_E_ARG", "QW_F32", "QW_F64", "QW_BEAM_STANDING_PARAXIAL", "QW_LOOP_INSTANCE"):
+        assert must in consts, must
+    for name, value in consts.items():
+        assert getattr(qw, name, None) == value, name
+
+
 def test_library_exports_every_declared_symbol():
     L = qw.lib()
     for name in declared_functions():
