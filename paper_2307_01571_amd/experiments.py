@@ -254,9 +254,64 @@ def diffraction(prec=qw.QW_F64, px_kl=-1.0, n_orders=(-3, -2, -1, 0, 1, 2, 3)):
             "bands": {k: (list(map(float, v)) if isinstance(v, np.ndarray) else v) for k, v in obs.items()}}
 
 
+def drift(kl_mc=0.1, eps=0.02, checkpoints=10, chunk=10_000):
+    """FP32 against FP64 along one run of the scan's family (Sec. IV.B
+    set-up), both propagated side by side on their own streams: at
+    `checkpoints` evenly spaced step counts, the spin-flip density at the
+    diffracted peak, P_+1, P_flip and the norm of each, and the FP32
+    relative errors.  The growth of those errors with the step count (the
+    log-log slope over the later checkpoints) tells a systematic per-step
+    bias (slope 1) from accumulated rounding (slope 1/2)."""
+    import torch
+    cfg = setup(kl_mc=kl_mc, eps=eps)
+    total_steps = cfg["steps"]
+    marks = [int(round(total_steps * (i + 1) / checkpoints)) for i in range(checkpoints)]
+    sims, streams = {}, {}
+    for name, prec in (("f32", qw.QW_F32), ("f64", qw.QW_F64)):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            sim = qw.Sim(cfg["grid"], prec, beam=cfg["beam"])
+            sim.set_frame(cfg["vy"], cfg["a_m"])
+            sim.init_packet(cfg["packet"])
+        sims[name], streams[name] = sim, st
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, rows = 0, []
+    n_max = cfg["obs"].n_max
+    for mark in marks:
+        while done < mark:
+            n = min(chunk, mark - done)
+            for name in sims:
+                with torch.cuda.stream(streams[name]):
+                    sims[name].step(n, done * cfg["dt"], cfg["dt"])
+            done += n
+            torch.cuda.synchronize()
+        row = {"steps": done}
+        for name in sims:
+            with torch.cuda.stream(streams[name]):
+                obs = qw.unpack_observables(sims[name].observables(cfg["obs"]), n_max)
+                maps = sims[name].momentum_maps()
+            total = float(np.sum(maps[..., 0]))
+            cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
+            row[name] = {"c_minus_sq": cm / total, "P_plus1": float(obs["P"][n_max + 1]), "P_flip": obs["P_flip"],
+                         "norm": obs["norm"]}
+        row["rel_err"] = {k: abs(row["f32"][k] - row["f64"][k]) / abs(row["f64"][k])
+                          for k in ("c_minus_sq", "P_plus1", "P_flip")}
+        row["norm_diff"] = row["f32"]["norm"] - row["f64"]["norm"]
+        rows.append(row)
+        _log(f"  drift: {done}/{total_steps} steps, {time.perf_counter() - t0:.1f} s, rel err {row['rel_err']}")
+    for sim in sims.values():
+        sim.close()
+    late = rows[len(rows) // 2:]
+    slopes = {k: loglog_slope([r["steps"] for r in late], [r["rel_err"][k] for r in late])
+              for k in ("c_minus_sq", "P_plus1", "P_flip")}
+    return {"config": {"kl_mc": kl_mc, "eps": eps, "grid": [cfg["grid"].nx, cfg["grid"].ny], "dt": cfg["dt"],
+                       "steps": total_steps}, "rows": rows, "loglog_slope_late_half": slopes}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction"])
+    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction", "drift"])
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--out", required=True)
     ap.add_argument("--kl", type=float, nargs="+", default=[0.05, 0.07, 0.1], help="hbar k_L / (m c) of the scans")
@@ -291,6 +346,8 @@ def main(argv=None):
             res[f"diff_kl{kl}"] = d
             res[f"slope_minus_kl{kl}"] = loglog_slope([x[0] for x in d], [x[1] for x in d])
             res[f"slope_plus_kl{kl}"] = loglog_slope([x[0] for x in d], [x[2] for x in d])
+    elif a.what == "drift":
+        res = drift(kl_mc=a.kl[0], eps=a.eps[0])
     else:
         res = {"E5": diffraction(prec, px_kl=-1.0), "E6": diffraction(prec, px_kl=0.0)}
     with open(a.out, "w") as f:

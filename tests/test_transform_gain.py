@@ -124,3 +124,27 @@ def test_gain_rejects_bad_lengths():
             qw.qw_transform_gain(n, F32)
     with pytest.raises(qw.QWError):
         qw.qw_transform_gain(1024, F32, 9)
+
+
+def test_per_bin_gains_of_the_float_transform_pair():
+    """The round trip of one row pass in free flight (inverse, then forward
+    transform, 1/N) as an exact linear map with the float-rounded constants:
+    nearly diagonal, with a gain per frequency bin whose spread (a few 1e-8
+    per step) is not removed by the mean-gain factor in K.  Two bins that
+    hold different diffraction orders (p_x = -k_L and +k_L of a 2048-point
+    row over 80 wavelengths: bins -80 and +80) decay at rates that differ by
+    about 6e-8 per step, so their populations drift apart linearly in the
+    number of steps (about 1.5% after 2.5e5 steps)."""
+    n = 2048
+    F = stockham(np.eye(n, dtype=complex), PLANS_F32[n], f32=True)
+    M = F @ np.conj(F) / n
+    g2 = np.abs(np.diag(M)) ** 2
+    off = float(np.sum(np.abs(M - np.diag(np.diag(M))) ** 2)) / n
+    mean = float(np.mean(g2))
+    print(f"mean |g|^2 - 1 = {mean - 1:+.3e}, spread (std) {np.std(g2):.3e}; "
+          f"bin -80: {g2[-80] - 1:+.3e}, bin +80: {g2[80] - 1:+.3e}; off-diagonal {off:.2e} per row")
+    assert abs((mean - 1) - 2 * (qw.qw_transform_gain(n, F32) - 1)) < 1e-9   # two transforms per round trip
+    assert 1e-8 < np.std(g2) < 1e-7
+    assert 3e-8 < abs(g2[80] - g2[-80]) < 1e-7
+    assert off < 1e-13
+
