@@ -130,11 +130,9 @@ def test_per_bin_gains_of_the_float_transform_pair():
     """The round trip of one row pass in free flight (inverse, then forward
     transform, 1/N) as an exact linear map with the float-rounded constants:
     nearly diagonal, with a gain per frequency bin whose spread (a few 1e-8
-    per step) is not removed by the mean-gain factor in K.  Two bins that
-    hold different diffraction orders (p_x = -k_L and +k_L of a 2048-point
-    row over 80 wavelengths: bins -80 and +80) decay at rates that differ by
-    about 6e-8 per step, so their populations drift apart linearly in the
-    number of steps (about 1.5% after 2.5e5 steps)."""
+    per step) the mean-gain factor in K does not remove.  Bins -80 and +80
+    of a 2048-point row over 80 wavelengths (p_x = -k_L and +k_L) lose
+    amounts per step that differ by about 6e-8."""
     n = 2048
     F = stockham(np.eye(n, dtype=complex), PLANS_F32[n], f32=True)
     M = F @ np.conj(F) / n
