@@ -309,10 +309,109 @@ def drift(kl_mc=0.1, eps=0.02, checkpoints=10, chunk=10_000):
                        "steps": total_steps}, "rows": rows, "loglog_slope_late_half": slopes}
 
 
+def _density_breakdown(cfg, maps):
+    """Sums of |phi|^2, |c+|^2, |c-|^2 and of the rest (negative energy) over
+    the momentum cells near the incoming packet (p_x = -k_L), near the +1
+    order (p_x = +k_L) and over all other cells."""
+    px, _ = momenta(cfg)
+    kl = cfg["kl"]
+    near_m = np.abs(px + kl) < kl / 2
+    near_p = np.abs(px - kl) < kl / 2
+    rest = ~(near_m | near_p)
+    comp = {"all": maps[..., 0], "c_plus": maps[..., 1], "c_minus": maps[..., 2],
+            "neg": maps[..., 0] - maps[..., 1] - maps[..., 2]}
+    return {f"{r}/{c}": float(np.sum(v[:, m])) for r, m in (("-1", near_m), ("+1", near_p), ("rest", rest))
+            for c, v in comp.items()}
+
+
+def drift_split(kl_mc=0.1, eps=0.02, split=0.5, checkpoints=5, chunk=10_000):
+    """FP64 through the first part of one run of the scan family (the share
+    split of its steps), then FP32 and FP64 continued from that same state
+    to the end, once with the field and once without it (QW_BEAM_NONE), all
+    four side by side on their own streams.  The growth of the FP32 relative
+    errors of P_+1 and of the flip density at the peak with and without the
+    field tells the free-flight operators (transforms, kinetic step) from the
+    interaction step as the source of FP32 drift; the breakdown of the
+    densities by momentum region and energy sign, at the first and the last
+    checkpoint, tells where the FP32 norm grows."""
+    import torch
+    cfg = setup(kl_mc=kl_mc, eps=eps)
+    total = cfg["steps"]
+    half = int(round(total * split))
+    base = qw.Sim(cfg["grid"], qw.QW_F64, beam=cfg["beam"])
+    base.set_frame(cfg["vy"], cfg["a_m"])
+    base.init_packet(cfg["packet"])
+    done = 0
+    while done < half:
+        n = min(chunk * 5, half - done)
+        base.step(n, done * cfg["dt"], cfg["dt"])
+        done += n
+        torch.cuda.synchronize()
+        _log(f"  drift_split: FP64 to the split, {done}/{half} steps")
+    state = base.psi.clone()
+    base.close()
+    off = W.BeamSpec(mode=qw.QW_BEAM_NONE)
+    runs = {}
+    for field, beam in (("on", cfg["beam"]), ("off", off)):
+        for name, prec in (("f32", qw.QW_F32), ("f64", qw.QW_F64)):
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                sim = qw.Sim(cfg["grid"], prec, beam=beam)
+                sim.set_frame(cfg["vy"], cfg["a_m"])
+                sim.psi.copy_(state.to(sim.psi.dtype))
+            runs[(field, name)] = (sim, st)
+    torch.cuda.synchronize()
+    marks = [half + int(round((total - half) * (i + 1) / checkpoints)) for i in range(checkpoints)]
+    n_max = cfg["obs"].n_max
+    rows, parts = [], {}
+    for mark in marks:
+        while done < mark:
+            n = min(chunk, mark - done)
+            for sim, st in runs.values():
+                with torch.cuda.stream(st):
+                    sim.step(n, done * cfg["dt"], cfg["dt"])
+            done += n
+            torch.cuda.synchronize()
+        row = {"steps": done, "after_split": done - half}
+        vals = {}
+        for key, (sim, st) in runs.items():
+            with torch.cuda.stream(st):
+                obs = qw.unpack_observables(sim.observables(cfg["obs"]), n_max)
+                maps = sim.momentum_maps()
+            tot = float(np.sum(maps[..., 0]))
+            cm, _, _ = peak_near(cfg, maps, cfg["kl"], C, col=2)
+            vals[key] = {"P_plus1": float(obs["P"][n_max + 1]), "c_minus_sq": cm / tot, "norm": obs["norm"]}
+            if mark in (marks[0], marks[-1]):
+                parts.setdefault(key, []).append(_density_breakdown(cfg, maps))
+        for field in ("on", "off"):
+            a, b = vals[(field, "f32")], vals[(field, "f64")]
+            row[field] = {k: abs(a[k] - b[k]) / abs(b[k]) for k in ("P_plus1", "c_minus_sq")}
+            row[field]["norm_diff"] = a["norm"] - b["norm"]
+            row[field]["P_plus1_f64"] = b["P_plus1"]
+            row[field]["c_minus_sq_f64"] = b["c_minus_sq"]
+        rows.append(row)
+        _log(f"  drift_split: {done}/{total} steps, on {row['on']}, off {row['off']}")
+    for sim, _ in runs.values():
+        sim.close()
+    # per region and component: FP32's relative change between the first and
+    # the last checkpoint minus FP64's, and FP64's share of the total at the end
+    growth = {}
+    for field in ("on", "off"):
+        (f32a, f32b), (f64a, f64b) = parts[(field, "f32")], parts[(field, "f64")]
+        tot = f64b["-1/all"] + f64b["+1/all"] + f64b["rest/all"]
+        growth[field] = {k: {"share_f64": f64b[k] / tot,
+                             "excess_rel_growth": (f32b[k] / f32a[k] - f64b[k] / f64a[k]) if f32a[k] > 0 and f64a[k] > 0 else None,
+                             "excess_abs_growth": (f32b[k] - f32a[k]) - (f64b[k] - f64a[k])}
+                         for k in f64b}
+    return {"config": {"kl_mc": kl_mc, "eps": eps, "grid": [cfg["grid"].nx, cfg["grid"].ny], "steps": total,
+                       "split": half}, "rows": rows, "growth_first_to_last_checkpoint": growth}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction", "drift"])
+    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction", "drift", "drift_split"])
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--split", type=float, default=0.5, help="drift_split: share of the run propagated in FP64 first")
     ap.add_argument("--out", required=True)
     ap.add_argument("--kl", type=float, nargs="+", default=[0.05, 0.07, 0.1], help="hbar k_L / (m c) of the scans")
     ap.add_argument("--eps", type=float, nargs="+", default=[0.01, 0.02, 0.05, 0.1], help="beam divergences of the scans")
@@ -348,6 +447,8 @@ def main(argv=None):
             res[f"slope_plus_kl{kl}"] = loglog_slope([x[0] for x in d], [x[2] for x in d])
     elif a.what == "drift":
         res = drift(kl_mc=a.kl[0], eps=a.eps[0])
+    elif a.what == "drift_split":
+        res = drift_split(kl_mc=a.kl[0], eps=a.eps[0], split=a.split)
     else:
         res = {"E5": diffraction(prec, px_kl=-1.0), "E6": diffraction(prec, px_kl=0.0)}
     with open(a.out, "w") as f:
