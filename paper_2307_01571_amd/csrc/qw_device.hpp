@@ -378,6 +378,19 @@ struct tw16 {
 // Pairs chosen for c^2 + s^2 closest to 1 instead carry phase errors of up
 // to about 1.3 units in the last place of one sign, which the band
 // probabilities pick up coherently, step after step.
+// The loss differs from bin to bin, and not evenly in +-k (2048 points: bins
+// +1 and -1 lose 0.7e-7 and 1.9e-7 per round trip), so the momentum
+// distribution drifts linearly in the step count: bins +80 and -80 (the
+// orders +-k_L of a 2048-point row over 80 wavelengths) part by 0.6% per
+// 1e5 steps.  With QW_F32_SPLIT_ROTATIONS = 1 each float constant is a pair
+// hi + lo (lo the float nearest the rest of the double value), and the lo
+// products enter the sum before the hi products are rounded, so the
+// constant is exact to about 2^-48 (a lo product added after the rounding is mostly lost: it
+// reaches half a unit in the last place only near the top of a binade).
+// That costs 2 FMAs per real product, about 3% of the 2048^2 FP32 step.
+#ifndef QW_F32_SPLIT_ROTATIONS
+#define QW_F32_SPLIT_ROTATIONS 0
+#endif
 // multiply by exp(-+2 pi i j / 16) with j a compile-time constant
 template <typename T, bool INV, int J>
 __device__ __forceinline__ cx<T> tw16mul(cx<T> a)
@@ -391,6 +404,13 @@ __device__ __forceinline__ cx<T> tw16mul(cx<T> a)
         const T c = (T)tw16::c[j];
         const T sj = (T)tw16::s[j];
         const T s = INV ? sj : -sj;
+        if constexpr (sizeof(T) == sizeof(float) && QW_F32_SPLIT_ROTATIONS) {
+            const T cl = (T)(tw16::c[j] - (double)c);
+            const T slj = (T)(tw16::s[j] - (double)sj);
+            const T sl = INV ? slj : -slj;
+            return cx<T>{fmx(a.re, c, fmx(-a.im, s, fmx(a.re, cl, -(a.im * sl)))),
+                         fmx(a.re, s, fmx(a.im, c, fmx(a.re, sl, a.im * cl)))};
+        }
         return cx<T>{fmx(a.re, c, -(a.im * s)), fmx(a.re, s, a.im * c)};
     }
 }

@@ -194,14 +194,21 @@ inline qw::BeamArgs beam_args(const qw_grid& g, const qw_beam& b)
 // (R = 16), or w16^(2 q s) with q = r mod 2 (R = 8), each on a quarter of
 // its energy; R = 2, 4 use only +-1 and +-i.  Averaged over the inputs, the
 // passes' gains multiply.  Forward and inverse transforms use conjugate
-// pairs of the same magnitudes.
+// pairs of the same magnitudes.  Built with QW_F32_SPLIT_ROTATIONS = 1 the
+// rotation constants are hi + lo float pairs, exact to about 2^-48, and only
+// the twiddles lose norm.
+#ifndef QW_F32_SPLIT_ROTATIONS
+#define QW_F32_SPLIT_ROTATIONS 0
+#endif
 inline double transform_gain_f32(const int* radices, int count)
 {
     auto mag2 = [](double angle) {
         const double c = (double)(float)std::cos(angle), s = (double)(float)std::sin(angle);
         return c * c + s * s;
     };
-    auto w16 = [&](int j) { return (j & 3) == 0 ? 1.0 : mag2(2.0 * kPi * (j & 15) / 16.0); };
+    auto w16 = [&](int j) {
+        return (j & 3) == 0 || QW_F32_SPLIT_ROTATIONS ? 1.0 : mag2(2.0 * kPi * (j & 15) / 16.0);
+    };
     double gain = 1.0;
     int ns = 1;
     for (int p = 0; p < count; ++p) {

@@ -407,9 +407,45 @@ def drift_split(kl_mc=0.1, eps=0.02, split=0.5, checkpoints=5, chunk=10_000):
                        "split": half}, "rows": rows, "growth_first_to_last_checkpoint": growth}
 
 
+def bin_gains(kl_mc=0.1, eps=0.02, bins=(-240, -160, -80, -1, 0, 1, 80, 160, 240), steps=40_000):
+    """Norm gain per step of single momentum cells under the free step of
+    the scan family's grid and frame (field off): a plane wave at (kx, ky =
+    0) with one unit spinor component, propagated steps steps in FP32 and in
+    FP64; returns log(norm after / norm before) / steps per bin and
+    component.  The step's gain for one cell, whatever the other cells
+    hold, measured on the kernels themselves."""
+    import torch
+    cfg = setup(kl_mc=kl_mc, eps=eps)
+    g = cfg["grid"]
+    off = W.BeamSpec(mode=qw.QW_BEAM_NONE)
+    ix = torch.arange(g.nx, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, prec in (("f32", qw.QW_F32), ("f64", qw.QW_F64)):
+        rows = {}
+        for kx in bins:
+            gains = []
+            for comp in range(4):
+                sim = qw.Sim(g, prec, beam=off)
+                sim.set_frame(cfg["vy"], cfg["a_m"])
+                w = torch.zeros((g.ny, g.nx, 4), dtype=torch.complex128, device="cuda")
+                w[:, :, comp] = torch.exp(2j * math.pi * kx * ix / g.nx)[None, :] / math.sqrt(g.nx * g.ny)
+                sim.psi.copy_(w.to(sim.psi.dtype))
+                n0 = float((sim.psi.to(torch.complex128).abs() ** 2).sum())
+                sim.step(steps, 0.0, cfg["dt"])
+                torch.cuda.synchronize()
+                n1 = float((sim.psi.to(torch.complex128).abs() ** 2).sum())
+                sim.close()
+                gains.append(math.log(n1 / n0) / steps)
+            rows[str(kx)] = gains
+            _log(f"  bin_gains {name} kx {kx}: " + " ".join(f"{v:+.3e}" for v in gains))
+        out[name] = rows
+    return {"config": {"kl_mc": kl_mc, "grid": [g.nx, g.ny], "steps": steps,
+                       "transform_gain_x": qw.qw_transform_gain(g.nx, qw.QW_F32)}, "gain_per_step": out}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction", "drift", "drift_split"])
+    ap.add_argument("what", choices=["showcase", "scaling", "longitudinal", "diffraction", "drift", "drift_split", "bin_gains"])
     ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
     ap.add_argument("--split", type=float, default=0.5, help="drift_split: share of the run propagated in FP64 first")
     ap.add_argument("--out", required=True)
@@ -447,6 +483,8 @@ def main(argv=None):
             res[f"slope_plus_kl{kl}"] = loglog_slope([x[0] for x in d], [x[2] for x in d])
     elif a.what == "drift":
         res = drift(kl_mc=a.kl[0], eps=a.eps[0])
+    elif a.what == "bin_gains":
+        res = bin_gains(kl_mc=a.kl[0], eps=a.eps[0])
     elif a.what == "drift_split":
         res = drift_split(kl_mc=a.kl[0], eps=a.eps[0], split=a.split)
     else:

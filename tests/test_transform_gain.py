@@ -146,3 +146,28 @@ def test_per_bin_gains_of_the_float_transform_pair():
     assert 3e-8 < abs(g2[80] - g2[-80]) < 1e-7
     assert off < 1e-13
 
+
+
+def test_a_lo_part_survives_only_before_the_rounding():
+    """The split rotation constants (hi + lo floats): the lo product must
+    enter the sum before the hi product is rounded.  With float values
+    emulated exactly in double (a float product is exact there), rounding
+    a c_hi + a c_lo once gives a c on average; adding a c_lo to the rounded
+    a c_hi changes it only where the lo product reaches half a unit in the
+    last place (near the top of a binade), so most of the constant's
+    rounding stays, the same at every call."""
+    rng = np.random.default_rng(7)
+    a = rng.uniform(0.5, 2.0, 200_000).astype(np.float32).astype(np.float64)
+    c = np.cos(2 * np.pi / 16)
+    hi = float(np.float32(c))
+    lo = float(np.float32(c - hi))
+    assert lo != 0.0 and abs(lo) < 2.0 ** -24 * abs(hi)
+    f32 = lambda x: x.astype(np.float32).astype(np.float64)
+    before = f32(a * hi + a * lo)          # one rounding: fma(a, hi, a lo)
+    after = f32(f32(a * hi) + a * lo)      # fma(a, lo, fl(a hi))
+    hi_only = f32(a * hi)
+    rel = lambda y: float(np.mean((y - a * c) / (a * c)))
+    assert abs(rel(before)) < 2e-10                          # unbiased
+    assert abs(rel(hi_only) - (hi - c) / c) < 2e-10          # the constant's rounding, coherent
+    assert np.mean(after != hi_only) < 0.1                   # the lo part is mostly lost
+    assert abs(rel(after)) > 0.8 * abs(rel(hi_only))
